@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the two-component Shan-Chen D3Q19 relaxation run.
+
+Workload (the single-droplet throughput case): a 128 x 128 x 64 box with
+walls at z = 0 and 63, a cap of radius 24 of A on the floor (rho 0.7 / 0.04,
+noise 1e-3, seed 0), tau = 1, psi = rho, g_ab = g_wall = 0.12, wall
+asymmetry rho_wall_A - rho_wall_B = 0.2.  A "step" is one lattice time step
+(pull-stream + bounce-back, Shan-Chen and wall force, velocity shift, BGK
+collide, fused in one kernel); the timed region also takes the FP64
+mass/momentum reduction and both contact-angle estimators every 100 steps,
+as a relaxation run does.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  Extra objects: roofline of the fused step kernel
+(algorithmic bytes 2 species x 19 x (read + write) x sizeof(real) per fluid
+node), the FP32 run, FP32-vs-FP64 results after --theta-steps steps, the
+adjoint/forward cost ratio (64 x 64 x 48), the batched sweep against
+sequential launches (64 droplets drawn from seed 0), and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D3Q19 2-comp MLUPS & % HBM roofline; adjoint/forward cost; FP32 vs FP64 dtheta"
+COUNTERS = os.path.join(ROOT, "profiles", "step_fused_128x128x64_f64_counters.json")
+KERNEL_SOURCES = ["paper_0910_3915_amd/csrc/step.hip", "paper_0910_3915_amd/csrc/common.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def fluid_nodes(solid):
+    import numpy as np
+    return int(np.count_nonzero(np.asarray(solid) == 0))
+
+
+def timed_relaxation(scd, W, torch, dtype, steps, warmup, obs_every, tile, stream):
+    """MLUPS of the relaxation run and the per-launch time of the step kernel."""
+    c = W.config_throughput(delta=0.2, dtype=dtype)
+    L = scd.Lattice(c["params"], c["solid"], stream=stream)
+    if tile is not None:
+        L.set_tile(*tile)
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    nf = fluid_nodes(c["solid"])
+    L.graph_capture(obs_every)
+    reps_w = max(1, warmup // obs_every)
+    reps = max(1, steps // obs_every)
+    for _ in range(reps_w):
+        L.graph_replay(1)
+    L.observables()
+    torch.cuda.synchronize()
+    # timed region: steps with observables every obs_every steps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.graph_replay(1)
+        L.observables()
+        L.contact_angle(c["ca"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nsteps = reps * obs_every
+    # kernel-only region on the kernel's stream: average launch duration
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.graph_replay(reps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / nsteps
+    ca = L.contact_angle(c["ca"])
+    variant, zc = L.tile()
+    tx, ty, zmarch, waves = scd.tile_list()[variant]
+    return {"mlups": nf * nsteps / wall / 1e6, "ms_per_step": wall * 1e3 / nsteps, "steps": nsteps,
+            "launch_ms": launch_ms, "fluid_nodes": nf, "theta_e1": ca["theta_e1"],
+            "theta_e2": ca["theta_e2"],
+            "tile": {"tx": tx, "ty": ty, "zmarch": zmarch, "waves_per_simd": waves, "zchunk": zc}}
+
+
+def roofline(res, bytes_per_node, traffic):
+    achieved = bytes_per_node * res["fluid_nodes"] / (res["launch_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_step (fused pull-stream, force, collide)",
+            "bytes_per_fluid_node": bytes_per_node, "launch_us": round(res["launch_ms"] * 1e3, 2)}
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    d = json.load(open(COUNTERS))
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def autotuned_tile(scd, W, dtype, stream):
+    c = W.config_throughput(delta=0.2, dtype=dtype)
+    L = scd.Lattice(c["params"], c["solid"], stream=stream)
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    best, ms = L.autotune(10, None)
+    return tuple(best), ms
+
+
+def fp32_vs_fp64(scd, W, torch, steps, tile64, tile32, stream):
+    import numpy as np
+    out = {}
+    dens = {}
+    for dt, tile in (("f64", tile64), ("f32", tile32)):
+        c = W.config_throughput(delta=0.2, dtype=dt)
+        L = scd.Lattice(c["params"], c["solid"], stream=stream)
+        if tile is not None:
+            L.set_tile(*tile)
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(steps)
+        out[dt] = L.contact_angle(c["ca"])
+        dens[dt] = L.density().cpu().numpy()
+    return {"steps": steps,
+            "max_abs_drho": float(np.max(np.abs(dens["f64"] - dens["f32"]))),
+            "theta_e1_f64": out["f64"]["theta_e1"], "theta_e1_f32": out["f32"]["theta_e1"],
+            "theta_e2_f64": out["f64"]["theta_e2"], "theta_e2_f32": out["f32"]["theta_e2"],
+            "dtheta_e1": abs(out["f64"]["theta_e1"] - out["f32"]["theta_e1"]),
+            "dtheta_e2": abs(out["f64"]["theta_e2"] - out["f32"]["theta_e2"])}
+
+
+def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
+    c = W.config_gradient(dtype=dtype)
+    L = scd.Lattice(c["params"], c["solid"], adjoint=True, stream=stream)
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    L.step(200)
+    st = L.get_state()
+    lam = L.ca_seed(c["ca"], 1.0)
+    lam2 = torch.empty_like(lam)
+    L.graph_capture(20)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    L.graph_replay(nsteps // 20)
+    e[1].record(stream)
+    L.adjoint_reset()
+    e[2].record(stream)
+    a, b = lam, lam2
+    for _ in range(nsteps):
+        L.adjoint_step(st, a, b, accumulate=True)
+        a, b = b, a
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    g = L.adjoint_read()
+    fwd = e[0].elapsed_time(e[1]) / nsteps
+    adj = e[2].elapsed_time(e[3]) / nsteps
+    return {"workload": "64x64x48 droplet r=14, " + dtype, "forward_ms": round(fwd, 4),
+            "adjoint_ms": round(adj, 4), "ratio": round(adj / fwd, 3),
+            "grad_finite": all(x == x for x in g)}
+
+
+def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):
+    draws = W.batch_draw(n, seed=0)
+    cases = [W.droplet_case(d["nx"], d["ny"], d["nz"], d["radius"], d["g_ab"], d["delta"], dtype="f32")
+             for d in draws]
+    nf = sum(fluid_nodes(c["solid"]) for c in cases)
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=stream)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    B.graph_capture(20)
+    B.graph_replay(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.graph_replay(steps // 20)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del B
+    torch.cuda.empty_cache()
+    lats = []
+    for c in cases:
+        L = scd.Lattice(c["params"], c["solid"], stream=stream)
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        lats.append(L)
+    for L in lats:
+        L.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for L in lats:
+            L.step(1)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"droplets": n, "fluid_nodes": nf, "dtype": "f32", "steps": steps,
+            "batched_mlups": round(nf * steps / tb / 1e6, 1),
+            "sequential_mlups": round(nf * steps / ts / 1e6, 1),
+            "speedup": round(ts / tb, 3)}
+
+
+def cpu_baseline(W, seconds):
+    import oracle
+    c = W.config_throughput(delta=0.2)
+    L = oracle.Lattice(c["params"], c["solid"])
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    nf = fluid_nodes(c["solid"])
+    L.step(1)  # first touch
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        L.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 1000:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"128x128x64 droplet, FP64, {steps} steps ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--obs-every", type=int, default=100)
+    ap.add_argument("--theta-steps", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true", help="main workload only")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.obs_every % 2:
+        args.obs_every += 1
+
+    import torch
+    import paper_0910_3915_amd as scd
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    tile64 = tile32 = None  # library default variant and z-chunk
+    if not args.no_autotune:
+        tile64, ms64 = autotuned_tile(scd, W, "f64", stream)
+        tile32, ms32 = autotuned_tile(scd, W, "f32", stream)
+        log(f"autotune: f64 {tile64} {ms64:.4f} ms/step, f32 {tile32} {ms32:.4f} ms/step")
+
+    log("timing FP64 relaxation run")
+    r64 = timed_relaxation(scd, W, torch, "f64", args.steps, args.warmup, args.obs_every, tile64, stream)
+    log(json.dumps(r64))
+    result = {
+        "metric": METRIC, "value": round(r64["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": r64["steps"], "warmup": args.warmup, "ms_per_step": round(r64["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded droplet, no dataset)",
+        "config": {"workload": "single droplet 128x128x64, cap r=24, g_ab=g_wall=0.12, tau=1, "
+                               "rho_wall=(0.6,0.4), FP64, observables every %d steps" % args.obs_every,
+                   "fluid_nodes": r64["fluid_nodes"], "tile": r64["tile"], "parallelism": "single GPU"},
+        "roofline": roofline(r64, 608, measured_traffic()),
+    }
+    if not args.no_extras:
+        log("timing FP32 relaxation run")
+        r32 = timed_relaxation(scd, W, torch, "f32", args.steps, args.warmup, args.obs_every, tile32, stream)
+        result["fp32"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
+                          "ms_per_step": round(r32["ms_per_step"], 5), "tile": r32["tile"],
+                          "roofline": roofline(r32, 304, None)}
+        log("FP32 vs FP64 after %d steps" % args.theta_steps)
+        result["fp32_vs_fp64"] = fp32_vs_fp64(scd, W, torch, args.theta_steps, tile64, tile32, stream)
+        log("adjoint / forward cost")
+        result["adjoint"] = {"f64": adjoint_cost(scd, W, torch, stream, "f64"),
+                             "f32": adjoint_cost(scd, W, torch, stream, "f32")}
+        log("batched vs sequential")
+        result["batched"] = batched_vs_sequential(scd, W, torch, stream)
+    log("CPU oracle baseline")
+    result["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

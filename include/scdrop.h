@@ -1,0 +1,256 @@
+/*
+ * scdrop.h -- C ABI of libscdrop, the MI355X (gfx950) engine for the
+ * two-component Shan-Chen lattice Boltzmann model on a D3Q19 lattice with
+ * interacting walls, and for the contact-angle observable measured on it.
+ *
+ * Method (Schmieschek & Harting, "Contact angle determination in
+ * multicomponent lattice Boltzmann simulations"):
+ *   Sec. 2, Eq. (LBeqs)    per-species streaming + BGK collision
+ *   Sec. 2, Eq. (Equil)    third-order equilibrium on D3Q19 (c_s^2 = 1/3)
+ *   Sec. 2, Eq. (SCforce)  Shan-Chen force over the 18 nearest neighbours,
+ *                          psi = rho (default) or psi = 1 - exp(-rho)
+ *   Sec. 2, velocity shift du^a = tau^a F^a / rho^a in the equilibrium
+ *   Sec. 2, walls          mid-grid bounce-back; wall nodes act as a species
+ *                          of constant density with its own coupling
+ *   Sec. 2, order param.   phi = rho_A - rho_B, interface at phi = 0
+ *   Sec. 3, Eq. (geoCA)    contact angle from the height and base of the cap,
+ *                          measured against a reference layer above the wall
+ * The adjoint step, the checkpointed gradient driver and the batched launch
+ * are extensions beyond the paper.
+ *
+ * Conventions
+ *   - Node index i = (z * ny + y) * nx + x, x fastest; N = nx * ny * nz.
+ *     All three axes are periodic; walls come only from the solid mask.
+ *   - Population state ("pop"): structure of arrays, element
+ *     pop[(a * 19 + k) * N + i] for species a in {0 = A, 1 = B} and
+ *     velocity k in the order: rest; +x, -x, +y, -y, +z, -z;
+ *     (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1),
+ *     (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1).
+ *     Element type double (SCD_F64) or float (SCD_F32).  The stored state is
+ *     post-collision; entries at solid nodes are never read.
+ *   - Density arrays are double, 2 * N elements, rho[a * N + i].
+ *   - "d_" pointers are device pointers on the current HIP device; "h_"
+ *     pointers are host pointers.  The caller allocates every device buffer
+ *     and keeps it alive while a handle uses it; the library allocates only
+ *     its small host-side handle and never frees caller memory.
+ *   - All work is enqueued on the handle's stream in order.  Calls that
+ *     return results to the host (observables, contact angle, gradients)
+ *     synchronise that stream.
+ *   - A handle is not thread-safe; distinct handles may be used from
+ *     different threads.
+ *   - Every call returns a status; on failure scd_last_error() gives a
+ *     message (thread-local, valid until the next call on that thread).
+ */
+#ifndef SCDROP_H
+#define SCDROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t scd_status;
+#define SCD_OK 0
+#define SCD_EINVAL (-1)        /* bad argument or parameter */
+#define SCD_EDEVICE (-2)       /* HIP runtime error */
+#define SCD_ENONFINITE (-3)    /* NaN or Inf in the state */
+#define SCD_ENOINTERFACE (-4)  /* no droplet on the measurement column */
+#define SCD_EUNSUPPORTED (-5)  /* valid request this build cannot serve */
+
+#define SCD_F64 0
+#define SCD_F32 1
+
+#define SCD_PSI_RHO 0          /* psi(rho) = rho */
+#define SCD_PSI_EXP 1          /* psi(rho) = 1 - exp(-rho), the paper's form */
+
+#define SCD_WITH_ADJOINT 1     /* scd_params.flags: reserve adjoint scratch */
+
+typedef struct {
+  int32_t nx, ny, nz;          /* each >= 1; 19 * N * sizeof(real) < 4 GiB */
+  int32_t dtype;               /* SCD_F64 or SCD_F32 */
+  int32_t psi;                 /* SCD_PSI_RHO or SCD_PSI_EXP */
+  int32_t flags;               /* SCD_WITH_ADJOINT or 0 */
+  double tau[2];               /* relaxation times of A and B, > 1/2;
+                                  kinematic viscosity (2 tau - 1)/6 (Sec. 4) */
+  double g_ab;                 /* fluid-fluid coupling, >= 0 (repulsive) */
+  double g_wall[2];            /* coupling felt by A and by B at wall nodes */
+  double rho_wall[2];          /* wall content of A and of B, >= 0: species a
+                                  feels the other species' wall content */
+  double w_axis, w_diag;       /* per-direction weights of the force sum;
+                                  1, 1 is the paper's unweighted sum */
+} scd_params;
+
+typedef struct {
+  double mass[2];              /* sum over fluid nodes of rho^A, rho^B (FP64) */
+  double momentum[3];          /* sum over fluid nodes and species of C_k c_k */
+  int32_t finite;              /* 1 if every population is finite */
+  int32_t pad;
+  int64_t step;                /* steps taken since scd_init_equilibrium */
+} scd_obs;
+
+typedef struct {
+  int32_t ic, jc;              /* column through the droplet axis */
+  int32_t z_solid_top;         /* top solid layer under the droplet; the wall
+                                  surface is half a spacing above it */
+  int32_t offset;              /* reference layer = z_solid_top + offset (5) */
+  double eps;                  /* half width of the smoothed indicator (0.2) */
+} scd_ca_cfg;
+
+typedef struct {
+  /* E1: zero crossings of phi (Sec. 3) */
+  double theta_e1, h_e1, a_e1, R_e1, aref_e1, H_e1;
+  /* E2: smoothed indicator chi = S((phi + eps) / 2 eps), differentiable */
+  double theta_e2, h_e2, a_e2, R_e2, aref_e2, H_e2;
+  double cx, cy;               /* centroid of phi > 0 in the reference layer */
+  int32_t flags;               /* SCD_CA_* */
+  int32_t pad;
+} scd_ca;                      /* angles in degrees, lengths in lattice units */
+
+#define SCD_CA_NO_REF 1        /* phi <= 0 at the reference layer: E1 measured
+                                  the base directly in the first fluid layer */
+#define SCD_CA_E1_FLAT 2       /* E1 cap has no real base: reported as 180 */
+#define SCD_CA_E2_FLAT 4       /* E2 likewise */
+#define SCD_CA_RAY_LIMIT 8     /* a half-chord ray found no crossing in L/2 */
+#define SCD_CA_NO_APEX 16      /* no crossing above the reference layer */
+#define SCD_CA_NO_DROP 32      /* phi <= 0 on the first fluid node of the
+                                  column: angles are NaN, ENOINTERFACE */
+#define SCD_CA_E2_EMPTY 64     /* E2 column height <= 0 */
+
+typedef struct scd_lattice scd_lattice;
+
+/* Bytes of one population buffer and of the work area for these params.
+ * The work area holds link masks, reduction partials, observable scratch
+ * and (with SCD_WITH_ADJOINT) the adjoint scratch. */
+scd_status scd_sizes(const scd_params* p, size_t* pop_bytes, size_t* work_bytes);
+
+/* Create a handle.  d_solid: N bytes, nonzero = wall node.  d_pop0, d_pop1:
+ * the two population buffers (ping-pong); d_work: work area; all 256-byte
+ * aligned device memory of the sizes given by scd_sizes.  stream: a
+ * hipStream_t (NULL = default stream).  Validates the parameters (tau > 1/2,
+ * rho_wall >= 0, g >= 0, dims >= 1) and writes *out. */
+scd_status scd_create(const scd_params* p, const uint8_t* d_solid, void* d_pop0, void* d_pop1,
+                      void* d_work, void* stream, scd_lattice** out);
+scd_status scd_destroy(scd_lattice* h);
+
+/* Change the physical parameters; dims, dtype and flags must not change. */
+scd_status scd_set_params(scd_lattice* h, const scd_params* p);
+scd_status scd_set_stream(scd_lattice* h, void* stream);
+
+/* Sec. 2 initial state: C_k^a = zeta_k rho^a (fluid at rest) at fluid nodes,
+ * from d_rho_a, d_rho_b (N doubles each).  Resets the step counter. */
+scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const double* d_rho_b);
+
+/* Advance nsteps >= 0 time steps of Eq. (LBeqs) (asynchronous). */
+scd_status scd_step(scd_lattice* h, int64_t nsteps);
+int64_t scd_step_count(const scd_lattice* h);
+
+/* Copy the current state out / in (pop layout, device to device). */
+scd_status scd_get_state(scd_lattice* h, void* d_dst);
+scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step);
+
+/* rho^a = sum_k C_k^a at fluid nodes, 0 at wall nodes; d_rho: 2 * N doubles */
+scd_status scd_density(scd_lattice* h, double* d_rho);
+
+/* Mass per species, total momentum and the all-finite flag, accumulated in
+ * FP64 with a fixed reduction order (bit-reproducible).  Synchronises.
+ * Returns SCD_ENONFINITE (with *out filled) if any population is not finite. */
+scd_status scd_observables(scd_lattice* h, scd_obs* h_out);
+
+/* Contact angle of the current state (Sec. 3), both estimators.
+ * Synchronises.  Returns SCD_ENOINTERFACE with NaN angles and
+ * SCD_CA_NO_DROP when phi <= 0 at the column's first fluid node. */
+scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* h_out);
+
+/* ---- adjoint (extension) ---- */
+/* d_lambda (pop layout, dtype of the lattice) := dL/dC of the current state
+ * for L = theta_E2 (radians) times dL_dtheta.  Synchronises. */
+scd_status scd_ca_seed(scd_lattice* h, const scd_ca_cfg* cfg, double dL_dtheta, void* d_lambda);
+/* One reverse step.  d_state_t: C^t (the state the forward step started
+ * from); d_lam_in: lambda^{t+1} = dL/dC^{t+1}; d_lam_out: lambda^t (must not
+ * alias d_lam_in).  With h_dparams != NULL: h_dparams[5] += dL/d{rho_wall_A,
+ * rho_wall_B, g_ab, g_wall_A, g_wall_B} of this step, and the call
+ * synchronises.  With h_dparams == NULL the step's gradient is added to a
+ * device accumulator instead (no synchronisation); see scd_adjoint_reset /
+ * scd_adjoint_read.  Needs SCD_WITH_ADJOINT. */
+scd_status scd_adjoint_step(scd_lattice* h, const void* d_state_t, const void* d_lam_in,
+                            void* d_lam_out, double* h_dparams);
+/* Zero the device accumulator of the parameter gradient (asynchronous). */
+scd_status scd_adjoint_reset(scd_lattice* h);
+/* Copy the accumulator (5 doubles, same order) to the host.  Synchronises. */
+scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
+
+/* Checkpointed gradient of L = (theta_E2 - target_deg)^2 (deg^2) after
+ * nsteps steps from the densities d_rho_a, d_rho_b.  Forward: runs nsteps,
+ * storing the state every ckpt_every steps into d_ckpt (ceil(nsteps /
+ * ckpt_every) population buffers).  Backward: for each segment in reverse,
+ * recomputes its states into d_seg (ckpt_every buffers) and applies the
+ * adjoint steps; d_lam holds 2 population buffers of scratch.
+ * h_out[0] = loss, h_out[1] = theta_E2 (deg); h_grad[5] = dL/dparams. */
+scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
+                            int64_t nsteps, int64_t ckpt_every, void* d_ckpt,
+                            const scd_ca_cfg* cfg, double target_deg, double* h_out);
+scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t ckpt_every,
+                             const void* d_ckpt, void* d_seg, void* d_lam,
+                             const scd_ca_cfg* cfg, double target_deg, double* h_grad);
+
+/* ---- launch control (extension) ---- */
+/* The fused step is compiled in several variants: a tile of tx * ty
+ * threads (one column each), a z-march variant (0: the collided plane's
+ * populations stay in registers; 1: they are pulled again from cache, which
+ * frees registers) and a minimum number of waves per SIMD.  scd_tile_list
+ * writes up to cap rows (tx, ty, z-march variant, waves) into h_rows (4
+ * int32 per row) and the number of variants into *n.  A lattice uses one
+ * variant index and a z-chunk of zc planes per workgroup. */
+scd_status scd_tile_list(int32_t* h_rows, int32_t cap, int32_t* n);
+scd_status scd_tile_set(scd_lattice* h, int32_t variant, int32_t zc);
+scd_status scd_tile_get(const scd_lattice* h, int32_t* variant, int32_t* zc);
+/* Time every compiled variant with several z-chunks on this lattice and
+ * keep the fastest: h_best[2] = variant, zc; *h_ms = its time per step.  The
+ * trial steps advance (and overwrite) the lattice state: re-initialise it
+ * afterwards.  cache_path (may be NULL): JSON-lines file of earlier results
+ * keyed by dims, dtype, device and variant count; a hit skips the trials. */
+scd_status scd_autotune(scd_lattice* h, int32_t steps_per_trial, const char* cache_path,
+                        int32_t* h_best, double* h_ms);
+
+/* Capture nsteps (even, > 0) steps into a HIP graph on the handle's stream,
+ * then replay it; scd_graph_replay advances the state by reps * nsteps. */
+scd_status scd_graph_capture(scd_lattice* h, int64_t nsteps);
+scd_status scd_graph_replay(scd_lattice* h, int64_t reps);
+
+/* ---- batched launch (extension) ----
+ * n lattices of any sizes (one dtype) advance together: each step is one
+ * persistent launch whose workgroups walk a list of (lattice, tile) items.
+ * The caller provides one device arena of scd_batch_sizes bytes that holds
+ * every lattice's two population buffers and work area, the per-lattice
+ * descriptors and the work list.  d_solid: host array of n device pointers
+ * to the solid masks (kept alive by the caller). */
+typedef struct scd_batch scd_batch;
+scd_status scd_batch_sizes(int32_t n, const scd_params* p, size_t* arena_bytes);
+scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const* d_solid,
+                            void* d_arena, void* stream, scd_batch** out);
+scd_status scd_batch_destroy(scd_batch* b);
+/* A lattice handle that views member i (observables, contact angle,
+ * density, state copies); owned by the batch, do not destroy or step it. */
+scd_status scd_batch_lattice(scd_batch* b, int32_t i, scd_lattice** view);
+scd_status scd_batch_init_equilibrium(scd_batch* b, int32_t i, const double* d_rho_a,
+                                      const double* d_rho_b);
+/* Step variant (see scd_tile_list), z-chunk and number of persistent
+ * workgroups (grid). */
+scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t grid);
+scd_status scd_batch_step(scd_batch* b, int64_t nsteps);
+scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps);
+scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps);
+
+/* Fill each of the 38 * N entries of the current state with value
+ * (for tests of the observables) */
+scd_status scd_fill_state(scd_lattice* h, double value);
+
+const char* scd_last_error(void);
+const char* scd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,424 @@
+"""ctypes binding of libscdrop (include/scdrop.h).
+
+Argument marshalling only: every computation runs in the HIP library.
+PyTorch provides device memory (tensors) and streams.  The library must be
+built (``__graft_entry__.build()`` or ``python -m paper_0910_3915_amd.build``);
+nothing here falls back to another implementation.
+"""
+import ctypes
+import os
+import re
+
+import torch  # loaded first: libscdrop binds to the HIP runtime torch loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscdrop.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "scdrop.h")
+
+SCD_OK, SCD_EINVAL, SCD_EDEVICE, SCD_ENONFINITE, SCD_ENOINTERFACE, SCD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SCD_F64, SCD_F32 = 0, 1
+SCD_WITH_ADJOINT = 1
+CA_FLAGS = {"NO_REF": 1, "E1_FLAT": 2, "E2_FLAT": 4, "RAY_LIMIT": 8, "NO_APEX": 16,
+            "NO_DROP": 32, "E2_EMPTY": 64}
+
+
+class ScdParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("psi", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tau", ctypes.c_double * 2), ("g_ab", ctypes.c_double),
+                ("g_wall", ctypes.c_double * 2), ("rho_wall", ctypes.c_double * 2),
+                ("w_axis", ctypes.c_double), ("w_diag", ctypes.c_double)]
+
+
+class ScdObs(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double * 2), ("momentum", ctypes.c_double * 3),
+                ("finite", ctypes.c_int32), ("pad", ctypes.c_int32), ("step", ctypes.c_int64)]
+
+
+class ScdCaCfg(ctypes.Structure):
+    _fields_ = [("ic", ctypes.c_int32), ("jc", ctypes.c_int32),
+                ("z_solid_top", ctypes.c_int32), ("offset", ctypes.c_int32),
+                ("eps", ctypes.c_double)]
+
+
+class ScdCa(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "theta_e1", "h_e1", "a_e1", "R_e1", "aref_e1", "H_e1",
+        "theta_e2", "h_e2", "a_e2", "R_e2", "aref_e2", "H_e2", "cx", "cy")] + [
+        ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ScdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"scdrop status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+_PROTOS = {
+    "scd_sizes": [ctypes.POINTER(ScdParams), ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+    "scd_create": [ctypes.POINTER(ScdParams), _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_VP)],
+    "scd_destroy": [_VP],
+    "scd_set_params": [_VP, ctypes.POINTER(ScdParams)],
+    "scd_set_stream": [_VP, _VP],
+    "scd_init_equilibrium": [_VP, _VP, _VP],
+    "scd_step": [_VP, _I64],
+    "scd_get_state": [_VP, _VP],
+    "scd_set_state": [_VP, _VP, _I64],
+    "scd_fill_state": [_VP, _D],
+    "scd_density": [_VP, _VP],
+    "scd_observables": [_VP, ctypes.POINTER(ScdObs)],
+    "scd_contact_angle": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
+    "scd_ca_seed": [_VP, ctypes.POINTER(ScdCaCfg), _D, _VP],
+    "scd_adjoint_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_D)],
+    "scd_adjoint_reset": [_VP],
+    "scd_adjoint_read": [_VP, ctypes.POINTER(_D)],
+    "scd_ckpt_forward": [_VP, _VP, _VP, _I64, _I64, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
+    "scd_ckpt_backward": [_VP, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
+    "scd_tile_set": [_VP, _I32, _I32],
+    "scd_tile_get": [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
+    "scd_tile_list": [ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I32)],
+    "scd_autotune": [_VP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_D)],
+    "scd_graph_capture": [_VP, _I64],
+    "scd_graph_replay": [_VP, _I64],
+    "scd_batch_sizes": [_I32, ctypes.POINTER(ScdParams), ctypes.POINTER(ctypes.c_size_t)],
+    "scd_batch_create": [_I32, ctypes.POINTER(ScdParams), ctypes.POINTER(_VP), _VP, _VP, ctypes.POINTER(_VP)],
+    "scd_batch_destroy": [_VP],
+    "scd_batch_lattice": [_VP, _I32, ctypes.POINTER(_VP)],
+    "scd_batch_init_equilibrium": [_VP, _I32, _VP, _VP],
+    "scd_batch_set_tile": [_VP, _I32, _I32, _I32],
+    "scd_batch_step": [_VP, _I64],
+    "scd_batch_graph_capture": [_VP, _I64],
+    "scd_batch_graph_replay": [_VP, _I64],
+}
+
+
+def header_symbols():
+    """Names of the functions that include/scdrop.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:scd_status|int64_t|const char\*)\s+(scd_\w+)\(", text, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _PROTOS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _I32
+        L.scd_step_count.argtypes = [_VP]
+        L.scd_step_count.restype = _I64
+        L.scd_last_error.restype = ctypes.c_char_p
+        L.scd_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != SCD_OK:
+        raise ScdError(status, lib().scd_last_error().decode())
+    return status
+
+
+def make_params(p, adjoint=False):
+    sp = ScdParams()
+    sp.nx, sp.ny, sp.nz = p["nx"], p["ny"], p["nz"]
+    sp.dtype = SCD_F64 if p.get("dtype", "f64") == "f64" else SCD_F32
+    sp.psi = p.get("psi", 0)
+    sp.flags = SCD_WITH_ADJOINT if adjoint else 0
+    sp.tau[0], sp.tau[1] = p["tau"]
+    sp.g_ab = p["g_ab"]
+    sp.g_wall[0], sp.g_wall[1] = p["g_wall"]
+    sp.rho_wall[0], sp.rho_wall[1] = p["rho_wall"]
+    sp.w_axis = p.get("w_axis", 1.0)
+    sp.w_diag = p.get("w_diag", 1.0)
+    return sp
+
+
+def make_ca_cfg(c):
+    cfg = ScdCaCfg()
+    cfg.ic, cfg.jc = c["ic"], c["jc"]
+    cfg.z_solid_top, cfg.offset = c["z_solid_top"], c["offset"]
+    cfg.eps = c.get("eps", 0.2)
+    return cfg
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return ctypes.c_void_p(None)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _torch_dtype(sp):
+    return torch.float64 if sp.dtype == SCD_F64 else torch.float32
+
+
+def _alloc_bytes(nbytes, device):
+    # 256-byte aligned device memory (the caching allocator aligns to 512)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _device_f64(a, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+
+class Lattice:
+    """One lattice: owns its device buffers (torch) and an scd_lattice handle."""
+
+    def __init__(self, params, solid, device="cuda", adjoint=False, stream=None):
+        self.params = dict(params)
+        self.device = torch.device(device)
+        self.sp = make_params(params, adjoint)
+        self.shape = (params["nz"], params["ny"], params["nx"])
+        self.N = params["nx"] * params["ny"] * params["nz"]
+        pop_b, work_b = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().scd_sizes(ctypes.byref(self.sp), ctypes.byref(pop_b), ctypes.byref(work_b)))
+        self.pop_bytes = pop_b.value
+        self.dtype = _torch_dtype(self.sp)
+        self.solid = torch.as_tensor(solid, dtype=torch.uint8).reshape(self.shape).to(self.device).contiguous()
+        self.pop = [torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.work = _alloc_bytes(work_b.value, self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().scd_create(ctypes.byref(self.sp), _ptr(self.solid), _ptr(self.pop[0]), _ptr(self.pop[1]),
+                               _ptr(self.work), _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().scd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # Stream order: inputs made on torch's current stream are read on the
+    # lattice's stream, outputs written there are read on torch's stream.
+    def _after_torch(self):
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _before_torch(self):
+        if self.stream is not None:
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    # -- method calls map one to one onto the C ABI
+    def set_params(self, params):
+        sp = make_params(params, bool(self.sp.flags & SCD_WITH_ADJOINT))
+        check(lib().scd_set_params(self.h, ctypes.byref(sp)))
+        self.sp = sp
+        self.params = dict(params)
+
+    def init_equilibrium(self, rho_a, rho_b):
+        ra = _device_f64(rho_a, self.device).reshape(-1)
+        rb = _device_f64(rho_b, self.device).reshape(-1)
+        self._after_torch()
+        check(lib().scd_init_equilibrium(self.h, _ptr(ra), _ptr(rb)))
+        self._keep = (ra, rb)  # alive until the kernel has read them
+
+    def step(self, n=1):
+        check(lib().scd_step(self.h, int(n)))
+
+    @property
+    def step_count(self):
+        return lib().scd_step_count(self.h)
+
+    def get_state(self, out=None):
+        if out is None:
+            out = torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device)
+        self._after_torch()
+        check(lib().scd_get_state(self.h, _ptr(out)))
+        self._before_torch()
+        return out
+
+    def set_state(self, src, step=0):
+        src = src.to(device=self.device, dtype=self.dtype).contiguous()
+        self._after_torch()
+        check(lib().scd_set_state(self.h, _ptr(src), int(step)))
+        self._keep = (src,)
+
+    def fill_state(self, value):
+        check(lib().scd_fill_state(self.h, float(value)))
+
+    def density(self):
+        out = torch.empty((2,) + self.shape, dtype=torch.float64, device=self.device)
+        self._after_torch()
+        check(lib().scd_density(self.h, _ptr(out)))
+        self._before_torch()
+        return out
+
+    def observables(self, raise_nonfinite=True):
+        o = ScdObs()
+        st = lib().scd_observables(self.h, ctypes.byref(o))
+        if st != SCD_ENONFINITE or raise_nonfinite:
+            check(st)
+        return {"mass": (o.mass[0], o.mass[1]), "momentum": tuple(o.momentum), "finite": bool(o.finite),
+                "step": o.step, "status": st}
+
+    def contact_angle(self, cfg):
+        out = ScdCa()
+        c = make_ca_cfg(cfg)
+        st = lib().scd_contact_angle(self.h, ctypes.byref(c), ctypes.byref(out))
+        if st not in (SCD_OK, SCD_ENOINTERFACE):
+            check(st)
+        d = {n: getattr(out, n) for n, _ in ScdCa._fields_ if n != "pad"}
+        d["status"] = st
+        return d
+
+    def ca_seed(self, cfg, dL_dtheta=1.0, out=None):
+        if out is None:
+            out = torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device)
+        c = make_ca_cfg(cfg)
+        self._after_torch()
+        check(lib().scd_ca_seed(self.h, ctypes.byref(c), float(dL_dtheta), _ptr(out)))
+        self._before_torch()
+        return out
+
+    def adjoint_step(self, state_t, lam_in, lam_out=None, accumulate=False):
+        """One reverse step.  accumulate=True adds the parameter gradient to
+        the device accumulator (no synchronisation) and returns None for it."""
+        if lam_out is None:
+            lam_out = torch.empty_like(lam_in)
+        self._after_torch()
+        if accumulate:
+            check(lib().scd_adjoint_step(self.h, _ptr(state_t), _ptr(lam_in), _ptr(lam_out), None))
+            self._before_torch()
+            return lam_out, None
+        dp = (ctypes.c_double * 5)()
+        check(lib().scd_adjoint_step(self.h, _ptr(state_t), _ptr(lam_in), _ptr(lam_out), dp))
+        self._before_torch()
+        return lam_out, list(dp)
+
+    def adjoint_reset(self):
+        check(lib().scd_adjoint_reset(self.h))
+
+    def adjoint_read(self):
+        g = (ctypes.c_double * 5)()
+        check(lib().scd_adjoint_read(self.h, g))
+        return list(g)
+
+    def tile(self):
+        """(variant index, z-chunk) of the fused step."""
+        a, b = _I32(), _I32()
+        check(lib().scd_tile_get(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_tile(self, variant, zc):
+        check(lib().scd_tile_set(self.h, int(variant), int(zc)))
+
+    def autotune(self, steps_per_trial=10, cache_path=None):
+        best = (_I32 * 2)()
+        ms = _D()
+        cp = cache_path.encode() if cache_path else None
+        check(lib().scd_autotune(self.h, int(steps_per_trial), cp, best, ctypes.byref(ms)))
+        return tuple(best), ms.value
+
+    def graph_capture(self, nsteps):
+        check(lib().scd_graph_capture(self.h, int(nsteps)))
+
+    def graph_replay(self, reps=1):
+        check(lib().scd_graph_replay(self.h, int(reps)))
+
+
+def tile_list():
+    """Compiled step variants as (tx, ty, z-march variant, waves per SIMD);
+    the list index is the variant index of set_tile."""
+    buf = (_I32 * 256)()
+    n = _I32()
+    check(lib().scd_tile_list(buf, 64, ctypes.byref(n)))
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(n.value)]
+
+
+def variant_index(tx, ty, zmarch, waves):
+    return tile_list().index((tx, ty, zmarch, waves))
+
+
+class Batch:
+    """Many lattices stepped together by one persistent launch per step."""
+
+    def __init__(self, params_list, solids, device="cuda", stream=None):
+        self.device = torch.device(device)
+        n = len(params_list)
+        arr = (ScdParams * n)(*[make_params(p) for p in params_list])
+        nbytes = ctypes.c_size_t()
+        check(lib().scd_batch_sizes(n, arr, ctypes.byref(nbytes)))
+        self.arena = _alloc_bytes(nbytes.value, self.device)
+        self.solids = [torch.as_tensor(s, dtype=torch.uint8).to(self.device).contiguous() for s in solids]
+        ptrs = (ctypes.c_void_p * n)(*[s.data_ptr() for s in self.solids])
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().scd_batch_create(n, arr, ptrs, _ptr(self.arena), _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+        self.params = [dict(p) for p in params_list]
+        self.n = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().scd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_equilibrium(self, i, rho_a, rho_b):
+        ra = _device_f64(rho_a, self.device).reshape(-1)
+        rb = _device_f64(rho_b, self.device).reshape(-1)
+        torch.cuda.synchronize(self.device)
+        check(lib().scd_batch_init_equilibrium(self.h, int(i), _ptr(ra), _ptr(rb)))
+        torch.cuda.synchronize(self.device)
+
+    def set_tile(self, variant, zc, grid):
+        check(lib().scd_batch_set_tile(self.h, int(variant), int(zc), int(grid)))
+
+    def step(self, n=1):
+        check(lib().scd_batch_step(self.h, int(n)))
+
+    def graph_capture(self, nsteps):
+        check(lib().scd_batch_graph_capture(self.h, int(nsteps)))
+
+    def graph_replay(self, reps=1):
+        check(lib().scd_batch_graph_replay(self.h, int(reps)))
+
+    def view(self, i):
+        """(handle, shape, dtype) of member i for observables and state copies."""
+        v = ctypes.c_void_p()
+        check(lib().scd_batch_lattice(self.h, int(i), ctypes.byref(v)))
+        return _View(v, self.params[i], self.device, self.stream)
+
+
+class _View(Lattice):
+    """Lattice interface over a batch member (buffers owned by the batch)."""
+
+    def __init__(self, h, params, device, stream):  # noqa: D401 - no buffers of its own
+        self.h = h
+        self.stream = stream
+        self.params = dict(params)
+        self.device = device
+        self.sp = make_params(params)
+        self.shape = (params["nz"], params["ny"], params["nx"])
+        self.N = params["nx"] * params["ny"] * params["nz"]
+        self.dtype = _torch_dtype(self.sp)
+
+    def close(self):
+        self.h = None  # owned by the batch

@@ -1,0 +1,316 @@
+// adjoint.hip -- reverse-mode step of the fused lattice update (extension:
+// the exact transpose of every sub-step of Sec. 2, applied in reverse order).
+//
+// Given the state C^t and lambda' = dL/dC^{t+1}, one reverse step produces
+// lambda = dL/dC^t and the gradient with respect to the wall contents, the
+// fluid coupling and the wall couplings.  Three passes over the lattice:
+//   1. per fluid node: recompute the forward quantities (pull, moments, psi,
+//      force from the neighbours' post-stream densities, velocities) and
+//      transpose the collision (Eq. Equil), the velocity shift and the local
+//      part of the force; store q^a = psi^a dL/dF^a, D^a = dL/drho^a and
+//      E^a = dL/dj^a, and accumulate the parameter gradient;
+//   2. per fluid node: add the transposed force stencil, i.e. the gather
+//      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) into D;
+//   3. per node: transposed streaming with bounce-back, a gather of
+//      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k from x + c_k (or from x
+//      itself on the opposite velocity next to a wall).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace scd {
+
+// Streaming with bounce-back as in the forward step, addressed with 64-bit
+// element offsets from the state base.
+template <typename real>
+__device__ __forceinline__ void pull38_adj(const real* __restrict__ src, int N, int i,
+                                           const int (&xs)[3], const int (&ys)[3],
+                                           const int (&zs)[3], int nx, int ny, uint32_t lb,
+                                           real (&n)[38]) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int j = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const bool bb = (lb >> OPP[k]) & 1u;
+    const size_t off = bb ? (size_t)OPP[k] * N + i : (size_t)k * N + j;
+    n[k] = src[off];
+    n[Q + k] = src[(size_t)Q * N + off];
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+  if (lane == 0)
+    for (int j = 0; j < NV; ++j) sh[j * 16 + wave] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < NV; ++j) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += sh[j * 16 + w];
+      v[j] = s;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
+                                                   const real* __restrict__ lam,
+                                                   const uint32_t* __restrict__ links,
+                                                   const real* __restrict__ rhof, int nx, int ny,
+                                                   int nz, Phys<real> ph, real* __restrict__ qf,
+                                                   real* __restrict__ df, real* __restrict__ ef,
+                                                   double* __restrict__ partials) {
+  __shared__ double sh[5 * 16];
+  const int N = nx * ny * nz;
+  double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    if (lb & SELF_SOLID) {
+      for (int c = 0; c < 6; ++c) { qf[(size_t)c * N + i] = 0; ef[(size_t)c * N + i] = 0; }
+      df[i] = 0;
+      df[(size_t)N + i] = 0;
+      continue;
+    }
+    int xs[3], ys[3], zs[3];
+    axis3(i % nx, nx, xs);
+    axis3((i / nx) % ny, ny, ys);
+    axis3(i / (nx * ny), nz, zs);
+    real n[38];
+    pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
+    real rho[2], j[2][3];
+    moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
+    moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
+    real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
+    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k
+    real S[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    real pnb[Q][2];  // psi of both species at each neighbour (wall content at walls)
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const bool wall = (lb >> k) & 1u;
+      real pA, pB;
+      if (wall) {
+        pA = ph.psiw[0];
+        pB = ph.psiw[1];
+      } else {
+        const int y = nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
+        pA = psi_of(ph.psi_form, rhof[y]);
+        pB = psi_of(ph.psi_form, rhof[(size_t)N + y]);
+      }
+      pnb[k][0] = pA;
+      pnb[k][1] = pB;
+      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+      const real eA = w * (wall ? ph.gw[0] : ph.gab) * pB;
+      const real eB = w * (wall ? ph.gw[1] : ph.gab) * pA;
+      S[0][0] += CX[k] * eA; S[0][1] += CY[k] * eA; S[0][2] += CZ[k] * eA;
+      S[1][0] += CX[k] * eB; S[1][1] += CY[k] * eB; S[1][2] += CZ[k] * eB;
+    }
+    real F[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int d = 0; d < 3; ++d) F[a][d] = -psi[a] * S[a][d];
+    const real Rt = rho[0] * ph.inv_tau[0] + rho[1] * ph.inv_tau[1];
+    real up[3], u[2][3];
+    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) / Rt;
+    for (int a = 0; a < 2; ++a)
+      for (int d = 0; d < 3; ++d) u[a][d] = up[d] + ph.tau[a] * F[a][d] / rho[a];
+
+    // transpose of the collision C' = n (1 - 1/tau) + n^eq(rho, u) / tau
+    real drho[2] = {0, 0}, du[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const real ux = u[a][0], uy = u[a][1], uz = u[a][2];
+      const real uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const real g = lam[(size_t)(a * Q + k) * N + i] * ph.inv_tau[a];
+        const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+        const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
+                       real(4.5) * s * s * s - real(4.5) * uu * s;
+        const real Ps = real(3) + real(9) * s + real(13.5) * s * s - real(4.5) * uu;
+        const real Pq = real(-1.5) - real(4.5) * s;
+        const real wg = real(WEIGHT[k]) * g;
+        drho[a] += wg * P;
+        const real wr = wg * rho[a];
+        du[a][0] += wr * (Ps * CX[k] + real(2) * Pq * ux);
+        du[a][1] += wr * (Ps * CY[k] + real(2) * Pq * uy);
+        du[a][2] += wr * (Ps * CZ[k] + real(2) * Pq * uz);
+      }
+    }
+    // transpose of u^a = u' + tau^a F^a / rho^a, u' = J / R
+    real dF[2][3], dup[3] = {0, 0, 0};
+    for (int a = 0; a < 2; ++a) {
+      real Fdu = 0;
+      for (int d = 0; d < 3; ++d) {
+        dF[a][d] = ph.tau[a] / rho[a] * du[a][d];
+        Fdu += F[a][d] * du[a][d];
+        dup[d] += du[a][d];
+      }
+      drho[a] += -ph.tau[a] * Fdu / (rho[a] * rho[a]);
+    }
+    const real dupu = dup[0] * up[0] + dup[1] * up[1] + dup[2] * up[2];
+    for (int a = 0; a < 2; ++a) {
+      const real f = ph.inv_tau[a] / Rt;
+      for (int d = 0; d < 3; ++d) ef[(size_t)(a * 3 + d) * N + i] = dup[d] * f;
+      drho[a] += -dupu * f;
+    }
+    // transpose of the force: local part and parameter gradient
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int b = 1 - a;
+      const real dpsi_self = -(dF[a][0] * S[a][0] + dF[a][1] * S[a][1] + dF[a][2] * S[a][2]);
+      for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi[a] * dF[a][d];
+      df[(size_t)a * N + i] = drho[a] + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
+        const double t = (double)(-psi[a] * w * dFc);
+        if ((lb >> k) & 1u) {
+          gp[3 + a] += (double)ph.psiw[b] * t;
+          gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
+        } else {
+          gp[2] += (double)pnb[k][b] * t;
+        }
+      }
+    }
+  }
+  block_sum_adj<5>(gp, sh);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 5; ++c) partials[blockIdx.x * RED_STRIDE + c] = gp[c];
+}
+
+// D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b
+template <typename real>
+__global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict__ links,
+                                                     const real* __restrict__ rhof, int nx, int ny,
+                                                     int nz, Phys<real> ph,
+                                                     const real* __restrict__ qf,
+                                                     real* __restrict__ df) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    if (links[i] & SELF_SOLID) continue;
+    int xs[3], ys[3], zs[3];
+    axis3(i % nx, nx, xs);
+    axis3((i / nx) % ny, ny, ys);
+    axis3(i / (nx * ny), nz, zs);
+    real acc[2] = {0, 0};  // acc[b] from q of the other species
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const int x = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const real qc = qf[(size_t)(a * 3 + 0) * N + x] * CX[k] +
+                        qf[(size_t)(a * 3 + 1) * N + x] * CY[k] +
+                        qf[(size_t)(a * 3 + 2) * N + x] * CZ[k];
+        acc[1 - a] += w * qc;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      df[(size_t)b * N + i] += dpsi_of(ph.psi_form, rhof[(size_t)b * N + i]) * (-ph.gab * acc[b]);
+  }
+}
+
+// lambda_j(x) = dL/dn_j(x + c_j) if x + c_j is fluid, else dL/dn_{opp j}(x)
+template <typename real>
+__global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__ links, int nx,
+                                                    int ny, int nz, Phys<real> ph,
+                                                    const real* __restrict__ lam,
+                                                    const real* __restrict__ df,
+                                                    const real* __restrict__ ef,
+                                                    real* __restrict__ out) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    if (lb & SELF_SOLID) {
+#pragma unroll
+      for (int k = 0; k < 2 * Q; ++k) out[(size_t)k * N + i] = 0;
+      continue;
+    }
+    int xs[3], ys[3], zs[3];
+    axis3(i % nx, nx, xs);
+    axis3((i / nx) % ny, ny, ys);
+    axis3(i / (nx * ny), nz, zs);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const bool wall = (lb >> k) & 1u;
+      const int y = wall ? i : nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
+      const int kk = wall ? OPP[k] : k;
+      const int sx = wall ? -CX[k] : CX[k], sy = wall ? -CY[k] : CY[k], sz = wall ? -CZ[k] : CZ[k];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const real mu = df[(size_t)a * N + y] + ef[(size_t)(a * 3 + 0) * N + y] * sx +
+                        ef[(size_t)(a * 3 + 1) * N + y] * sy + ef[(size_t)(a * 3 + 2) * N + y] * sz +
+                        (real(1) - ph.inv_tau[a]) * lam[(size_t)(a * Q + kk) * N + y];
+        out[(size_t)(a * Q + k) * N + i] = mu;
+      }
+    }
+  }
+}
+
+template <typename real>
+static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
+                            const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
+                            real* rhof, real* qf, real* df, real* ef, double* partials,
+                            double* dparams, hipStream_t s) {
+  const Phys<real> ph = phys_cast<real>(phd);
+  const size_t N = (size_t)nx * ny * nz;
+  hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_local<real>, dim3(ADJ_BLOCKS), dim3(256), 0, s, C, lam_in, links, rhof,
+                     nx, ny, nz, ph, qf, df, ef, partials);
+  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
+  hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny, nz,
+                     ph, qf, df);
+  hipLaunchKernelGGL(k_adj_stream<real>, dim3(blocks), dim3(256), 0, s, links, nx, ny, nz, ph,
+                     lam_in, df, ef, lam_out);
+  return hipGetLastError();
+}
+
+__global__ void k_sum5(const double* __restrict__ partials, int nblocks, double* __restrict__ out,
+                       double* __restrict__ acc);
+
+hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
+                          const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
+                          void* rho_field, void* q_field, void* d_field, void* e_field,
+                          double* partials, double* dparams_dev, double* acc, hipStream_t s) {
+  hipError_t e;
+  if (dtype == 0)
+    e = adjoint_t<double>((const double*)state_t, (const double*)lam_in, (double*)lam_out, links,
+                          nx, ny, nz, ph, (double*)rho_field, (double*)q_field, (double*)d_field,
+                          (double*)e_field, partials, dparams_dev, s);
+  else
+    e = adjoint_t<float>((const float*)state_t, (const float*)lam_in, (float*)lam_out, links, nx,
+                         ny, nz, ph, (float*)rho_field, (float*)q_field, (float*)d_field,
+                         (float*)e_field, partials, dparams_dev, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum5, dim3(1), dim3(256), 0, s, partials, ADJ_BLOCKS, dparams_dev, acc);
+  return hipGetLastError();
+}
+
+// out = this step's parameter gradient; acc (if not NULL) += out, in step order
+__global__ __launch_bounds__(256) void k_sum5(const double* __restrict__ partials, int nblocks,
+                                              double* __restrict__ out, double* __restrict__ acc) {
+  __shared__ double sh[5 * 16];
+  double v[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int j = 0; j < 5; ++j) v[j] += partials[b * RED_STRIDE + j];
+  block_sum_adj<5>(v, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 5; ++j) {
+      out[j] = v[j];
+      if (acc) acc[j] += v[j];
+    }
+}
+
+__global__ void k_zero(double* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace scd

@@ -1,0 +1,901 @@
+// api.hip -- host side of the libscdrop C ABI (see include/scdrop.h):
+// handles, parameter validation, work-area layout, launch sequencing with
+// ping-pong buffers, observables read-back, the checkpointed adjoint driver,
+// HIP graph capture, the tile autotuner and the batched launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <iomanip>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "scdrop.h"
+
+using namespace scd;
+
+namespace {
+
+thread_local std::string g_err;
+
+scd_status fail(scd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SCD_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t real_size(int dtype) { return dtype == SCD_F64 ? 8 : 4; }
+
+struct WorkLayout {
+  size_t links, partials, result, phi, ca, adj_partials, adj_dparams, rho, q, d, e, total;
+};
+
+WorkLayout work_layout(const scd_params* p) {
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const size_t rs = real_size(p->dtype);
+  WorkLayout w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  w.links = take(N * 4);
+  w.partials = take((size_t)RED_BLOCKS * RED_STRIDE * 8);
+  w.result = take(16 * 8);
+  w.phi = take((2 * (size_t)p->nx * p->ny + p->nz) * 8);
+  w.ca = take(CA_SLOTS * 8);
+  if (p->flags & SCD_WITH_ADJOINT) {
+    w.adj_partials = take((size_t)ADJ_BLOCKS * RED_STRIDE * 8);
+    w.adj_dparams = take(16 * 8);  // [0, 8): last step, [8, 16): accumulator
+    w.rho = take(2 * N * rs);
+    w.q = take(6 * N * rs);
+    w.d = take(2 * N * rs);
+    w.e = take(6 * N * rs);
+  }
+  w.total = off;
+  return w;
+}
+
+scd_status validate(const scd_params* p) {
+  if (!p) return fail(SCD_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(SCD_EINVAL, "dimensions must be >= 1 (got %d %d %d)", p->nx, p->ny, p->nz);
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N >= (double)(1 << 30)) return fail(SCD_EINVAL, "lattice too large (%.0f nodes)", N);
+  if (p->nz >= 65536) return fail(SCD_EINVAL, "nz must be < 65536");
+  if (p->dtype != SCD_F64 && p->dtype != SCD_F32) return fail(SCD_EINVAL, "bad dtype %d", p->dtype);
+  // 32-bit byte offsets within one species' 19 planes
+  if (19.0 * N * (p->dtype == SCD_F64 ? 8 : 4) >= 4294967296.0)
+    return fail(SCD_EUNSUPPORTED, "19 planes of %.0f nodes exceed 4 GiB per species", N);
+  if (p->psi != SCD_PSI_RHO && p->psi != SCD_PSI_EXP) return fail(SCD_EINVAL, "bad psi %d", p->psi);
+  for (int a = 0; a < 2; ++a) {
+    if (!(p->tau[a] > 0.5) || !std::isfinite(p->tau[a]))
+      return fail(SCD_EINVAL, "tau[%d] = %g must be > 1/2", a, p->tau[a]);
+    if (!(p->rho_wall[a] >= 0.0) || !std::isfinite(p->rho_wall[a]))
+      return fail(SCD_EINVAL, "rho_wall[%d] = %g must be >= 0", a, p->rho_wall[a]);
+    if (!(p->g_wall[a] >= 0.0) || !std::isfinite(p->g_wall[a]))
+      return fail(SCD_EINVAL, "g_wall[%d] = %g must be >= 0", a, p->g_wall[a]);
+  }
+  if (!(p->g_ab >= 0.0) || !std::isfinite(p->g_ab)) return fail(SCD_EINVAL, "g_ab = %g must be >= 0", p->g_ab);
+  if (!std::isfinite(p->w_axis) || !std::isfinite(p->w_diag)) return fail(SCD_EINVAL, "bad weights");
+  return SCD_OK;
+}
+
+PhysD make_phys(const scd_params* p) {
+  PhysD ph;
+  for (int a = 0; a < 2; ++a) {
+    ph.tau[a] = p->tau[a];
+    ph.inv_tau[a] = 1.0 / p->tau[a];
+    ph.gw[a] = p->g_wall[a];
+    ph.psiw[a] = p->psi == SCD_PSI_EXP ? 1.0 - std::exp(-p->rho_wall[a]) : p->rho_wall[a];
+    ph.dpsiw[a] = p->psi == SCD_PSI_EXP ? std::exp(-p->rho_wall[a]) : 1.0;
+  }
+  ph.gab = p->g_ab;
+  ph.wa = p->w_axis;
+  ph.wd = p->w_diag;
+  ph.psi_form = p->psi;
+  return ph;
+}
+
+}  // namespace
+
+struct scd_lattice {
+  scd_params p;
+  PhysD ph;
+  size_t N;
+  WorkLayout wl;
+  const uint8_t* solid;
+  void* pop[2];
+  int cur;
+  char* work;
+  hipStream_t stream;
+  int64_t step;
+  int variant, zc, remap;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  int64_t graph_steps;
+  int graph_cur;
+  bool batch_view;  // buffers belong to a batch
+  uint32_t* links() const { return (uint32_t*)(work + wl.links); }
+  double* wd(size_t off) const { return (double*)(work + off); }
+  void* wv(size_t off) const { return (void*)(work + off); }
+};
+
+namespace {
+
+int default_variant() {
+  int v = variant_find(64, 4, 0, 1);
+  return v < 0 ? 0 : v;
+}
+
+void default_tile(scd_lattice* h) {
+  h->variant = default_variant();
+  h->zc = std::min(16, h->p.nz);
+  h->remap = 1;
+}
+
+scd_status enqueue_steps(scd_lattice* h, int64_t nsteps) {
+  for (int64_t s = 0; s < nsteps; ++s) {
+    HIPCHK(launch_step(h->p.dtype, h->pop[h->cur], h->pop[1 - h->cur], h->links(), h->p.nx, h->p.ny,
+                       h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream));
+    h->cur ^= 1;
+    h->step += 1;
+  }
+  return SCD_OK;
+}
+
+void drop_graph(scd_lattice* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->graph_steps = 0;
+}
+
+scd_status check_cfg(const scd_lattice* h, const scd_ca_cfg* c) {
+  if (!c) return fail(SCD_EINVAL, "ca cfg is NULL");
+  if (c->ic < 0 || c->ic >= h->p.nx || c->jc < 0 || c->jc >= h->p.ny)
+    return fail(SCD_EINVAL, "column (%d, %d) outside the lattice", c->ic, c->jc);
+  if (c->z_solid_top < 0 || c->offset < 1 || c->z_solid_top + c->offset >= h->p.nz - 1)
+    return fail(SCD_EINVAL, "reference layer %d + %d outside the lattice", c->z_solid_top, c->offset);
+  if (!(c->eps > 0.0)) return fail(SCD_EINVAL, "eps must be > 0");
+  return SCD_OK;
+}
+
+CaDev ca_dev(const scd_ca_cfg* c) { return CaDev{c->ic, c->jc, c->z_solid_top, c->offset, c->eps}; }
+
+scd_status read_ca(scd_lattice* h, scd_ca* out, double* status_out) {
+  double r[CA_SLOTS];
+  HIPCHK(hipMemcpyAsync(r, h->wv(h->wl.ca), sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (out) {
+    out->theta_e1 = r[0]; out->h_e1 = r[1]; out->a_e1 = r[2]; out->R_e1 = r[3];
+    out->aref_e1 = r[4]; out->H_e1 = r[5];
+    out->theta_e2 = r[6]; out->h_e2 = r[7]; out->a_e2 = r[8]; out->R_e2 = r[9];
+    out->aref_e2 = r[10]; out->H_e2 = r[11];
+    out->cx = r[12]; out->cy = r[13];
+    out->flags = (int32_t)r[14];
+    out->pad = 0;
+  }
+  if (status_out) *status_out = r[15];
+  return SCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* scd_last_error(void) { return g_err.c_str(); }
+const char* scd_version(void) { return "scdrop 1.0 (gfx950)"; }
+
+scd_status scd_sizes(const scd_params* p, size_t* pop_bytes, size_t* work_bytes) {
+  scd_status st = validate(p);
+  if (st) return st;
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  if (pop_bytes) *pop_bytes = 2 * Q * N * real_size(p->dtype);
+  if (work_bytes) *work_bytes = work_layout(p).total;
+  return SCD_OK;
+}
+
+scd_status scd_create(const scd_params* p, const uint8_t* d_solid, void* d_pop0, void* d_pop1,
+                      void* d_work, void* stream, scd_lattice** out) {
+  scd_status st = validate(p);
+  if (st) return st;
+  if (!out || !d_solid || !d_pop0 || !d_pop1 || !d_work)
+    return fail(SCD_EINVAL, "NULL buffer passed to scd_create");
+  if (d_pop0 == d_pop1) return fail(SCD_EINVAL, "the two population buffers must differ");
+  if (((uintptr_t)d_pop0 | (uintptr_t)d_pop1 | (uintptr_t)d_work) & 255)
+    return fail(SCD_EINVAL, "device buffers must be 256-byte aligned");
+  scd_lattice* h = new scd_lattice();
+  h->p = *p;
+  h->ph = make_phys(p);
+  h->N = (size_t)p->nx * p->ny * p->nz;
+  h->wl = work_layout(p);
+  h->solid = d_solid;
+  h->pop[0] = d_pop0;
+  h->pop[1] = d_pop1;
+  h->cur = 0;
+  h->work = (char*)d_work;
+  h->stream = (hipStream_t)stream;
+  h->step = 0;
+  h->graph = nullptr;
+  h->gexec = nullptr;
+  h->graph_steps = 0;
+  h->graph_cur = 0;
+  h->batch_view = false;
+  default_tile(h);
+  hipError_t e = launch_links(d_solid, h->links(), p->nx, p->ny, p->nz, h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SCD_EDEVICE, "link-mask kernel: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return SCD_OK;
+}
+
+scd_status scd_destroy(scd_lattice* h) {
+  if (!h) return SCD_OK;
+  drop_graph(h);
+  delete h;
+  return SCD_OK;
+}
+
+scd_status scd_set_params(scd_lattice* h, const scd_params* p) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  scd_status st = validate(p);
+  if (st) return st;
+  if (p->nx != h->p.nx || p->ny != h->p.ny || p->nz != h->p.nz || p->dtype != h->p.dtype ||
+      p->flags != h->p.flags)
+    return fail(SCD_EINVAL, "dims, dtype and flags are fixed at creation");
+  h->p = *p;
+  h->ph = make_phys(p);
+  drop_graph(h);  // captured kernels carry the old parameters
+  return SCD_OK;
+}
+
+scd_status scd_set_stream(scd_lattice* h, void* stream) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  h->stream = (hipStream_t)stream;
+  drop_graph(h);
+  return SCD_OK;
+}
+
+scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const double* d_rho_b) {
+  if (!h || !d_rho_a || !d_rho_b) return fail(SCD_EINVAL, "NULL argument");
+  // the other buffer's wall-node entries are never written by a step: zero
+  // it so that every state copy is fully defined
+  HIPCHK(launch_fill(h->p.dtype, h->pop[1 - h->cur], 2 * Q * h->N, 0.0, h->stream));
+  HIPCHK(launch_init(h->p.dtype, h->pop[h->cur], d_rho_a, d_rho_b, h->links(), (int)h->N, h->stream));
+  h->step = 0;
+  return SCD_OK;
+}
+
+scd_status scd_step(scd_lattice* h, int64_t nsteps) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (nsteps < 0) return fail(SCD_EINVAL, "nsteps < 0");
+  return enqueue_steps(h, nsteps);
+}
+
+int64_t scd_step_count(const scd_lattice* h) { return h ? h->step : -1; }
+
+scd_status scd_get_state(scd_lattice* h, void* d_dst) {
+  if (!h || !d_dst) return fail(SCD_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(d_dst, h->pop[h->cur], 2 * Q * h->N * real_size(h->p.dtype),
+                        hipMemcpyDeviceToDevice, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step) {
+  if (!h || !d_src) return fail(SCD_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_src, 2 * Q * h->N * real_size(h->p.dtype),
+                        hipMemcpyDeviceToDevice, h->stream));
+  h->step = step;
+  return SCD_OK;
+}
+
+scd_status scd_fill_state(scd_lattice* h, double value) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  HIPCHK(launch_fill(h->p.dtype, h->pop[h->cur], 2 * Q * h->N, value, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_density(scd_lattice* h, double* d_rho) {
+  if (!h || !d_rho) return fail(SCD_EINVAL, "NULL argument");
+  HIPCHK(launch_density(h->p.dtype, h->pop[h->cur], h->links(), d_rho, (int)h->N, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_observables(scd_lattice* h, scd_obs* out) {
+  if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
+  HIPCHK(launch_observables(h->p.dtype, h->pop[h->cur], h->links(), (int)h->N,
+                            h->wd(h->wl.partials), h->wd(h->wl.result), h->stream));
+  double r[6];
+  HIPCHK(hipMemcpyAsync(r, h->wd(h->wl.result), sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out->mass[0] = r[0];
+  out->mass[1] = r[1];
+  out->momentum[0] = r[2];
+  out->momentum[1] = r[3];
+  out->momentum[2] = r[4];
+  out->finite = r[5] == 0.0 ? 1 : 0;
+  out->pad = 0;
+  out->step = h->step;
+  if (!out->finite) return fail(SCD_ENONFINITE, "%.0f non-finite populations", r[5]);
+  return SCD_OK;
+}
+
+scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out) {
+  if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
+  scd_status st = check_cfg(h, cfg);
+  if (st) return st;
+  HIPCHK(launch_contact_angle(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
+                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.ca), h->stream));
+  double status;
+  st = read_ca(h, out, &status);
+  if (st) return st;
+  if (status != 0.0) return fail(SCD_ENOINTERFACE, "no droplet on column (%d, %d)", cfg->ic, cfg->jc);
+  return SCD_OK;
+}
+
+scd_status scd_ca_seed(scd_lattice* h, const scd_ca_cfg* cfg, double dL_dtheta, void* d_lambda) {
+  if (!h || !d_lambda) return fail(SCD_EINVAL, "NULL argument");
+  scd_status st = check_cfg(h, cfg);
+  if (st) return st;
+  HIPCHK(launch_contact_angle(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
+                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.ca), h->stream));
+  HIPCHK(launch_ca_seed(h->p.dtype, h->links(), h->p.nx, h->p.ny, h->p.nz, ca_dev(cfg),
+                        h->wd(h->wl.phi), h->wd(h->wl.ca), dL_dtheta, d_lambda, h->stream));
+  scd_ca ca;
+  double status;
+  st = read_ca(h, &ca, &status);
+  if (st) return st;
+  if (status != 0.0 || (ca.flags & SCD_CA_E2_EMPTY))
+    return fail(SCD_ENOINTERFACE, "no droplet for the E2 seed");
+  return SCD_OK;
+}
+
+static scd_status adjoint_enqueue(scd_lattice* h, const void* state_t, const void* lam_in,
+                                  void* lam_out, bool accumulate) {
+  HIPCHK(launch_adjoint(h->p.dtype, state_t, lam_in, lam_out, h->links(), h->p.nx, h->p.ny,
+                        h->p.nz, h->ph, h->wv(h->wl.rho), h->wv(h->wl.q), h->wv(h->wl.d),
+                        h->wv(h->wl.e), h->wd(h->wl.adj_partials), h->wd(h->wl.adj_dparams),
+                        accumulate ? h->wd(h->wl.adj_dparams) + 8 : nullptr, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_adjoint_reset(scd_lattice* h) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (!(h->p.flags & SCD_WITH_ADJOINT))
+    return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
+  HIPCHK(launch_zero(h->wd(h->wl.adj_dparams) + 8, 8, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_adjoint_read(scd_lattice* h, double* h_acc) {
+  if (!h || !h_acc) return fail(SCD_EINVAL, "NULL argument");
+  if (!(h->p.flags & SCD_WITH_ADJOINT))
+    return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
+  HIPCHK(hipMemcpyAsync(h_acc, h->wd(h->wl.adj_dparams) + 8, 5 * sizeof(double),
+                        hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_adjoint_step(scd_lattice* h, const void* d_state_t, const void* d_lam_in,
+                            void* d_lam_out, double* h_dparams) {
+  if (!h || !d_state_t || !d_lam_in || !d_lam_out) return fail(SCD_EINVAL, "NULL argument");
+  if (!(h->p.flags & SCD_WITH_ADJOINT))
+    return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
+  if (d_lam_in == d_lam_out) return fail(SCD_EINVAL, "lambda in and out must not alias");
+  scd_status st = adjoint_enqueue(h, d_state_t, d_lam_in, d_lam_out, h_dparams == nullptr);
+  if (st) return st;
+  if (!h_dparams) return SCD_OK;  // accumulated on the device, no synchronisation
+  double g[5];
+  HIPCHK(hipMemcpyAsync(g, h->wv(h->wl.adj_dparams), sizeof(g), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < 5; ++j) h_dparams[j] += g[j];
+  return SCD_OK;
+}
+
+static const double kRad2Deg = 57.295779513082320876798154814105;
+
+scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
+                            int64_t nsteps, int64_t K, void* d_ckpt, const scd_ca_cfg* cfg,
+                            double target_deg, double* h_out) {
+  if (!h || !d_ckpt || !h_out) return fail(SCD_EINVAL, "NULL argument");
+  if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and ckpt_every must be >= 1");
+  scd_status st = check_cfg(h, cfg);
+  if (st) return st;
+  st = scd_init_equilibrium(h, d_rho_a, d_rho_b);
+  if (st) return st;
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  for (int64_t t = 0; t < nsteps; t += K) {
+    HIPCHK(hipMemcpyAsync((char*)d_ckpt + (size_t)(t / K) * bytes, h->pop[h->cur], bytes,
+                          hipMemcpyDeviceToDevice, h->stream));
+    st = enqueue_steps(h, std::min(K, nsteps - t));
+    if (st) return st;
+  }
+  scd_ca ca;
+  st = scd_contact_angle(h, cfg, &ca);
+  if (st) return st;
+  h_out[0] = (ca.theta_e2 - target_deg) * (ca.theta_e2 - target_deg);
+  h_out[1] = ca.theta_e2;
+  return SCD_OK;
+}
+
+scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
+                             void* d_seg, void* d_lam, const scd_ca_cfg* cfg, double target_deg,
+                             double* h_grad) {
+  if (!h || !d_ckpt || !d_seg || !d_lam || !h_grad) return fail(SCD_EINVAL, "NULL argument");
+  if (!(h->p.flags & SCD_WITH_ADJOINT))
+    return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
+  if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (h->step != nsteps) return fail(SCD_EINVAL, "state is at step %lld, expected %lld",
+                                     (long long)h->step, (long long)nsteps);
+  scd_status st = check_cfg(h, cfg);
+  if (st) return st;
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  scd_ca ca;
+  st = scd_contact_angle(h, cfg, &ca);
+  if (st) return st;
+  const double dL_dtheta = 2.0 * (ca.theta_e2 - target_deg) * kRad2Deg;  // per radian
+  void* lam[2] = {d_lam, (char*)d_lam + bytes};
+  int lc = 0;
+  st = scd_ca_seed(h, cfg, dL_dtheta, lam[lc]);
+  if (st) return st;
+  st = scd_adjoint_reset(h);
+  if (st) return st;
+  const int64_t nseg = (nsteps + K - 1) / K;
+  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int64_t t0 = sgi * K, t1 = std::min(nsteps, t0 + K);
+    HIPCHK(hipMemcpyAsync(h->pop[h->cur], (const char*)d_ckpt + (size_t)sgi * bytes, bytes,
+                          hipMemcpyDeviceToDevice, h->stream));
+    h->step = t0;
+    for (int64_t t = t0; t < t1; ++t) {
+      HIPCHK(hipMemcpyAsync((char*)d_seg + (size_t)(t - t0) * bytes, h->pop[h->cur], bytes,
+                            hipMemcpyDeviceToDevice, h->stream));
+      st = enqueue_steps(h, 1);
+      if (st) return st;
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      st = adjoint_enqueue(h, (const char*)d_seg + (size_t)(t - t0) * bytes, lam[lc], lam[1 - lc],
+                           true);
+      if (st) return st;
+      lc = 1 - lc;
+    }
+  }
+  return scd_adjoint_read(h, h_grad);
+}
+
+// ---------------------------------------------------------------- tiles
+scd_status scd_tile_set(scd_lattice* h, int32_t variant, int32_t zc) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (variant < 0 || variant >= variant_count())
+    return fail(SCD_EINVAL, "variant %d is not compiled", variant);
+  if (zc < 1) return fail(SCD_EINVAL, "z-chunk must be >= 1");
+  h->variant = variant;
+  h->zc = std::min<int32_t>(zc, h->p.nz);
+  drop_graph(h);
+  return SCD_OK;
+}
+
+scd_status scd_tile_get(const scd_lattice* h, int32_t* variant, int32_t* zc) {
+  if (!h || !variant || !zc) return fail(SCD_EINVAL, "NULL argument");
+  *variant = h->variant;
+  *zc = h->zc;
+  return SCD_OK;
+}
+
+scd_status scd_tile_list(int32_t* rows, int32_t cap, int32_t* n) {
+  if (!n) return fail(SCD_EINVAL, "NULL argument");
+  const int cnt = variant_count();
+  for (int i = 0; i < cnt && i < cap; ++i)
+    variant_at(i, &rows[4 * i], &rows[4 * i + 1], &rows[4 * i + 2], &rows[4 * i + 3]);
+  *n = cnt;
+  return SCD_OK;
+}
+
+static std::string device_name() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName);
+}
+
+static std::string tune_key(const scd_lattice* h) {
+  std::ostringstream o;
+  o << h->p.nx << "x" << h->p.ny << "x" << h->p.nz << ":" << (h->p.dtype == SCD_F64 ? "f64" : "f32")
+    << ":" << device_name() << ":v" << variant_count();
+  return o.str();
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* best, double* ms) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const std::string k = "\"key\": \"" + key + "\"";
+    if (line.find(k) == std::string::npos) continue;
+    int v, zc;
+    double t;
+    const char* s = strstr(line.c_str(), "\"best\": [");
+    const char* m = strstr(line.c_str(), "\"ms\": ");
+    if (!s || !m) continue;
+    if (sscanf(s, "\"best\": [%d, %d]", &v, &zc) == 2 && sscanf(m, "\"ms\": %lf", &t) == 1) {
+      best[0] = v;
+      best[1] = zc;
+      *ms = t;
+      found = true;  // the last matching line wins
+    }
+  }
+  return found;
+}
+
+scd_status scd_autotune(scd_lattice* h, int32_t steps_per_trial, const char* cache_path,
+                        int32_t* best, double* best_ms) {
+  if (!h || !best || !best_ms) return fail(SCD_EINVAL, "NULL argument");
+  if (steps_per_trial < 2) return fail(SCD_EINVAL, "steps_per_trial must be >= 2");
+  const std::string key = tune_key(h);
+  int cached[2];
+  double cms;
+  if (cache_lookup(cache_path, key, cached, &cms) && cached[0] >= 0 && cached[0] < variant_count()) {
+    scd_status st = scd_tile_set(h, cached[0], cached[1]);
+    if (st) return st;
+    best[0] = cached[0];
+    best[1] = cached[1];
+    *best_ms = cms;
+    return SCD_OK;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double bms = 1e30;
+  int b[2] = {h->variant, h->zc};
+  const int zcs[] = {4, 8, 16, 32, 64};
+  for (int i = 0; i < variant_count(); ++i) {
+    int tx, ty, var, wpe;
+    variant_at(i, &tx, &ty, &var, &wpe);
+    if (tx > 2 * h->p.nx && tx > 16) continue;  // mostly idle lanes
+    for (int zc : zcs) {
+      if (zc > h->p.nz && zc != zcs[0]) continue;
+      scd_status st = scd_tile_set(h, i, zc);
+      if (st) return st;
+      st = enqueue_steps(h, 1);  // warm-up
+      if (st) return st;
+      HIPCHK(hipEventRecord(e0, h->stream));
+      st = enqueue_steps(h, steps_per_trial);
+      if (st) return st;
+      HIPCHK(hipEventRecord(e1, h->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / steps_per_trial;
+      if (per < bms) {
+        bms = per;
+        b[0] = i;
+        b[1] = std::min(zc, h->p.nz);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  scd_status st = scd_tile_set(h, b[0], b[1]);
+  if (st) return st;
+  best[0] = b[0];
+  best[1] = b[1];
+  *best_ms = bms;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << "{\"key\": \"" << key << "\", \"best\": [" << b[0] << ", " << b[1]
+      << "], \"ms\": " << std::setprecision(17) << bms << "}\n";
+  }
+  return SCD_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+scd_status scd_graph_capture(scd_lattice* h, int64_t nsteps) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (nsteps < 2 || (nsteps & 1)) return fail(SCD_EINVAL, "graph step count must be even and > 0");
+  if (!h->stream) return fail(SCD_EINVAL, "graph capture needs a non-default stream");
+  drop_graph(h);
+  const int cur0 = h->cur;
+  const int64_t step0 = h->step;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  scd_status st = enqueue_steps(h, nsteps);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  h->cur = cur0;  // capture does not run anything
+  h->step = step0;
+  if (st) return st;
+  if (e != hipSuccess) return fail(SCD_EDEVICE, "capture: %s", hipGetErrorString(e));
+  h->graph = g;
+  HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  h->graph_steps = nsteps;
+  h->graph_cur = cur0;
+  return SCD_OK;
+}
+
+scd_status scd_graph_replay(scd_lattice* h, int64_t reps) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (!h->gexec) return fail(SCD_EINVAL, "no captured graph");
+  if (h->cur != h->graph_cur) return fail(SCD_EINVAL, "buffer parity changed since capture");
+  for (int64_t r = 0; r < reps; ++r) {
+    HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+    h->step += h->graph_steps;
+  }
+  return SCD_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================= batch
+struct scd_batch {
+  int n;
+  int dtype;
+  std::vector<scd_lattice*> views;
+  char* arena;
+  size_t desc_off[2];  // descriptor tables for even and odd parity
+  size_t items_off;
+  int nitems;
+  int variant, zc, grid;
+  hipStream_t stream;
+  int parity;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  int64_t graph_steps;
+  int graph_parity;
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> pop0, pop1, work;
+  size_t desc[2], items, total;
+  int nitems;
+};
+
+int batch_items_of(const scd_params& p, int tx, int ty, int zc) {
+  return ((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty) * ((p.nz + zc - 1) / zc);
+}
+
+BatchLayout batch_layout(int n, const scd_params* p) {
+  BatchLayout L;
+  size_t off = 0;
+  L.nitems = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t pb, wb;
+    scd_sizes(&p[i], &pb, &wb);
+    L.pop0.push_back(off); off += align256(pb);
+    L.pop1.push_back(off); off += align256(pb);
+    L.work.push_back(off); off += align256(wb);
+  }
+  const size_t ds = latdev_size(p[0].dtype);
+  L.desc[0] = off; off += align256(ds * n);
+  L.desc[1] = off; off += align256(ds * n);
+  // room for the largest item list any compiled tile shape can produce
+  int maxitems = 0;
+  for (int t = 0; t < variant_count(); ++t) {
+    int a, b, v, w;
+    variant_at(t, &a, &b, &v, &w);
+    int m = 0;
+    for (int i = 0; i < n; ++i) m += batch_items_of(p[i], a, b, 1);
+    maxitems = std::max(maxitems, m);
+  }
+  L.items = off; off += align256((size_t)maxitems * 16);
+  L.total = off;
+  return L;
+}
+
+scd_status batch_upload(scd_batch* b) {
+  // descriptors for both parities and the (lattice, tile) work list
+  const size_t ds = latdev_size(b->dtype);
+  std::vector<char> d0(ds * b->n), d1(ds * b->n);
+  std::vector<int32_t> items;
+  for (int i = 0; i < b->n; ++i) {
+    scd_lattice* v = b->views[i];
+    latdev_fill(b->dtype, d0.data() + ds * i, v->pop[0], v->pop[1], v->links(), v->p.nx, v->p.ny,
+                v->p.nz, v->ph);
+    latdev_fill(b->dtype, d1.data() + ds * i, v->pop[1], v->pop[0], v->links(), v->p.nx, v->p.ny,
+                v->p.nz, v->ph);
+    const int zc = std::min(b->zc, v->p.nz);
+    int tx, ty, var, wpe;
+    variant_at(b->variant, &tx, &ty, &var, &wpe);
+    const int gx = (v->p.nx + tx - 1) / tx, gy = (v->p.ny + ty - 1) / ty;
+    const int gz = (v->p.nz + zc - 1) / zc;
+    for (int bz = 0; bz < gz; ++bz)
+      for (int by = 0; by < gy; ++by)
+        for (int bx = 0; bx < gx; ++bx) {
+          items.push_back(i);
+          items.push_back(bx);
+          items.push_back(by);
+          items.push_back((zc << 16) | (bz * zc));
+        }
+  }
+  b->nitems = (int)(items.size() / 4);
+  HIPCHK(hipMemcpyAsync(b->arena + b->desc_off[0], d0.data(), d0.size(), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipMemcpyAsync(b->arena + b->desc_off[1], d1.data(), d1.size(), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipMemcpyAsync(b->arena + b->items_off, items.data(), items.size() * 4, hipMemcpyHostToDevice,
+                        b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return SCD_OK;
+}
+
+void batch_drop_graph(scd_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+}
+
+scd_status batch_enqueue(scd_batch* b, int64_t nsteps) {
+  for (int64_t s = 0; s < nsteps; ++s) {
+    HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity], b->arena + b->items_off,
+                             b->nitems, b->grid, b->variant, b->stream));
+    b->parity ^= 1;
+    for (scd_lattice* v : b->views) {
+      v->cur = b->parity;
+      v->step += 1;
+    }
+  }
+  return SCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scd_status scd_batch_sizes(int32_t n, const scd_params* p, size_t* arena_bytes) {
+  if (n < 1 || !p || !arena_bytes) return fail(SCD_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    scd_status st = validate(&p[i]);
+    if (st) return st;
+    if (p[i].dtype != p[0].dtype) return fail(SCD_EINVAL, "all lattices of a batch share one dtype");
+  }
+  *arena_bytes = batch_layout(n, p).total;
+  return SCD_OK;
+}
+
+scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const* d_solid,
+                            void* d_arena, void* stream, scd_batch** out) {
+  size_t bytes;
+  scd_status st = scd_batch_sizes(n, p, &bytes);
+  if (st) return st;
+  if (!d_solid || !d_arena || !out) return fail(SCD_EINVAL, "NULL argument");
+  if ((uintptr_t)d_arena & 255) return fail(SCD_EINVAL, "arena must be 256-byte aligned");
+  BatchLayout L = batch_layout(n, p);
+  scd_batch* b = new scd_batch();
+  b->n = n;
+  b->dtype = p[0].dtype;
+  b->arena = (char*)d_arena;
+  b->desc_off[0] = L.desc[0];
+  b->desc_off[1] = L.desc[1];
+  b->items_off = L.items;
+  b->variant = default_variant();
+  b->zc = 16;
+  b->stream = (hipStream_t)stream;
+  b->parity = 0;
+  b->graph = nullptr;
+  b->gexec = nullptr;
+  b->graph_steps = 0;
+  b->graph_parity = 0;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  b->grid = cus * 4;
+  for (int i = 0; i < n; ++i) {
+    scd_lattice* v = nullptr;
+    st = scd_create(&p[i], d_solid[i], b->arena + L.pop0[i], b->arena + L.pop1[i],
+                    b->arena + L.work[i], stream, &v);
+    if (st) {
+      for (scd_lattice* w : b->views) scd_destroy(w);
+      delete b;
+      return st;
+    }
+    v->batch_view = true;
+    b->views.push_back(v);
+  }
+  st = batch_upload(b);
+  if (st) {
+    for (scd_lattice* w : b->views) scd_destroy(w);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return SCD_OK;
+}
+
+scd_status scd_batch_destroy(scd_batch* b) {
+  if (!b) return SCD_OK;
+  batch_drop_graph(b);
+  for (scd_lattice* v : b->views) scd_destroy(v);
+  delete b;
+  return SCD_OK;
+}
+
+scd_status scd_batch_lattice(scd_batch* b, int32_t i, scd_lattice** view) {
+  if (!b || !view || i < 0 || i >= b->n) return fail(SCD_EINVAL, "bad batch index");
+  *view = b->views[i];
+  return SCD_OK;
+}
+
+scd_status scd_batch_init_equilibrium(scd_batch* b, int32_t i, const double* d_rho_a,
+                                      const double* d_rho_b) {
+  if (!b || i < 0 || i >= b->n) return fail(SCD_EINVAL, "bad batch index");
+  scd_lattice* v = b->views[i];
+  v->cur = b->parity;
+  return scd_init_equilibrium(v, d_rho_a, d_rho_b);
+}
+
+scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t grid) {
+  if (!b) return fail(SCD_EINVAL, "NULL handle");
+  if (variant < 0 || variant >= variant_count())
+    return fail(SCD_EINVAL, "variant %d is not compiled", variant);
+  if (zc < 1 || grid < 1) return fail(SCD_EINVAL, "z-chunk and grid must be >= 1");
+  b->variant = variant;
+  b->zc = zc;
+  b->grid = grid;
+  for (scd_lattice* v : b->views) { v->variant = variant; v->zc = std::min(zc, v->p.nz); }
+  batch_drop_graph(b);
+  return batch_upload(b);
+}
+
+scd_status scd_batch_step(scd_batch* b, int64_t nsteps) {
+  if (!b) return fail(SCD_EINVAL, "NULL handle");
+  if (nsteps < 0) return fail(SCD_EINVAL, "nsteps < 0");
+  return batch_enqueue(b, nsteps);
+}
+
+scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps) {
+  if (!b) return fail(SCD_EINVAL, "NULL handle");
+  if (nsteps < 2 || (nsteps & 1)) return fail(SCD_EINVAL, "graph step count must be even and > 0");
+  if (!b->stream) return fail(SCD_EINVAL, "graph capture needs a non-default stream");
+  batch_drop_graph(b);
+  const int par0 = b->parity;
+  std::vector<int64_t> steps0;
+  for (scd_lattice* v : b->views) steps0.push_back(v->step);
+  HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  scd_status st = batch_enqueue(b, nsteps);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  b->parity = par0;
+  for (int i = 0; i < b->n; ++i) { b->views[i]->cur = par0; b->views[i]->step = steps0[i]; }
+  if (st) return st;
+  if (e != hipSuccess) return fail(SCD_EDEVICE, "capture: %s", hipGetErrorString(e));
+  b->graph = g;
+  HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+  b->graph_steps = nsteps;
+  b->graph_parity = par0;
+  return SCD_OK;
+}
+
+scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps) {
+  if (!b) return fail(SCD_EINVAL, "NULL handle");
+  if (!b->gexec) return fail(SCD_EINVAL, "no captured graph");
+  if (b->parity != b->graph_parity) return fail(SCD_EINVAL, "buffer parity changed since capture");
+  for (int64_t r = 0; r < reps; ++r) {
+    HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+    for (scd_lattice* v : b->views) v->step += b->graph_steps;
+  }
+  return SCD_OK;
+}
+
+}  // extern "C"

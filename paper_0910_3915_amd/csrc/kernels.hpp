@@ -1,0 +1,79 @@
+// kernels.hpp -- host-callable launchers of libscdrop's kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace scd {
+
+using PhysD = Phys<double>;
+
+template <typename real>
+inline Phys<real> phys_cast(const PhysD& d) {
+  Phys<real> r;
+  for (int a = 0; a < 2; ++a) {
+    r.tau[a] = (real)d.tau[a];
+    r.inv_tau[a] = (real)d.inv_tau[a];
+    r.gw[a] = (real)d.gw[a];
+    r.psiw[a] = (real)d.psiw[a];
+    r.dpsiw[a] = (real)d.dpsiw[a];
+  }
+  r.gab = (real)d.gab;
+  r.wa = (real)d.wa;
+  r.wd = (real)d.wd;
+  r.psi_form = d.psi_form;
+  return r;
+}
+
+// step.hip
+hipError_t launch_links(const uint8_t* solid, uint32_t* links, int nx, int ny, int nz,
+                        hipStream_t s);
+hipError_t launch_init(int dtype, void* pop, const double* ra, const double* rb,
+                       const uint32_t* links, int N, hipStream_t s);
+hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int N,
+                          hipStream_t s);
+hipError_t launch_stream_density(int dtype, const void* pop, const uint32_t* links, void* rho,
+                                 int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s);
+hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* links, int nx,
+                       int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
+                       hipStream_t s);
+hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
+                             int variant, hipStream_t s);
+size_t latdev_size(int dtype);
+void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_t* links, int nx,
+                 int ny, int nz, const PhysD& ph);
+int variant_count();
+void variant_at(int i, int* tx, int* ty, int* var, int* wpe);
+int variant_find(int tx, int ty, int var, int wpe);
+
+// observe.hip
+constexpr int RED_BLOCKS = 512;   // blocks of the observable reductions
+constexpr int RED_STRIDE = 8;     // doubles per block partial
+// contact-angle result slots (doubles) in the work area
+constexpr int CA_SLOTS = 32;
+hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int N,
+                              double* partials, double* result, hipStream_t s);
+struct CaDev {
+  int ic, jc, zs, off;
+  double eps;
+};
+hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                                int nz, CaDev cfg, double* phi_scratch, double* result,
+                                hipStream_t s);
+hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,
+                          const double* phi_scratch, const double* result, double dL_dtheta,
+                          void* lambda, hipStream_t s);
+
+// adjoint.hip
+constexpr int ADJ_BLOCKS = 512;
+hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
+                          const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
+                          void* rho_field, void* q_field, void* d_field, void* e_field,
+                          double* partials, double* dparams_dev, double* acc, hipStream_t s);
+hipError_t launch_zero(double* p, int n, hipStream_t s);
+
+}  // namespace scd

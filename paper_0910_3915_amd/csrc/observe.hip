@@ -1,0 +1,364 @@
+// observe.hip -- global reductions and the contact-angle observable on gfx950.
+//
+// Reductions accumulate in FP64 for both state precisions: a grid-stride
+// pass per thread, a wavefront butterfly (__shfl_xor, lowered to DPP / LDS
+// permutes), a cross-wave step in LDS, per-block partials, and a one-block
+// finish that adds the partials in a fixed order, so results are
+// bit-reproducible run to run.
+//
+// Contact angle (Sec. 3, Eq. geoCA): the order parameter phi = rho_A - rho_B
+// (Sec. 2) is evaluated on the reference layer, on the first fluid layer and
+// on the droplet's column; a one-block kernel then measures the cap with two
+// estimators:
+//   E1 -- zero crossings of phi by linear interpolation: apex height on the
+//         column, four half-chords in the reference layer, sphere radius
+//         R = (aref^2 + H^2) / 2H through the reference circle and the apex,
+//         base half-width a^2 = 2Rh - h^2 at the wall, theta = 2 atan(h / a);
+//   E2 -- the same geometry from sums of a smoothed indicator
+//         chi = S((phi + eps) / 2 eps), S(t) = 3t^2 - 2t^3 on [0, 1]: the
+//         column height H = chi(kref)/2 + sum of chi above it up to the top of
+//         the droplet, the reference area sum(chi) = pi aref^2.  E2 is a
+//         smooth function of the state and seeds the adjoint.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace scd {
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+  if (lane == 0)
+    for (int j = 0; j < NV; ++j) sh[j * 16 + wave] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < NV; ++j) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += sh[j * 16 + w];
+      v[j] = s;
+    }
+  __syncthreads();
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_obs_partial(const real* __restrict__ pop,
+                                                     const uint32_t* __restrict__ links, int N,
+                                                     double* __restrict__ partials) {
+  __shared__ double sh[6 * 16];
+  double v[6] = {0, 0, 0, 0, 0, 0};  // mass A, mass B, Px, Py, Pz, non-finite count
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    if (links[i] & SELF_SOLID) continue;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const double a = (double)pop[(size_t)k * N + i];
+      const double b = (double)pop[(size_t)(Q + k) * N + i];
+      if (!isfinite(a) || !isfinite(b)) v[5] += 1.0;
+      v[0] += a;
+      v[1] += b;
+      const double ab = a + b;
+      if (CX[k]) v[2] += CX[k] * ab;
+      if (CY[k]) v[3] += CY[k] * ab;
+      if (CZ[k]) v[4] += CZ[k] * ab;
+    }
+  }
+  block_sum<6>(v, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 6; ++j) partials[blockIdx.x * RED_STRIDE + j] = v[j];
+}
+
+// one block: partials of nblocks blocks -> result[0..5]
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partials,
+                                                      int nblocks, int nvals,
+                                                      double* __restrict__ result) {
+  __shared__ double sh[8 * 16];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int j = 0; j < nvals; ++j) v[j] += partials[b * RED_STRIDE + j];
+  block_sum<8>(v, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < nvals; ++j) result[j] = v[j];
+}
+
+hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int N,
+                              double* partials, double* result, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_obs_partial<double>, dim3(RED_BLOCKS), dim3(256), 0, s,
+                       (const double*)pop, links, N, partials);
+  else
+    hipLaunchKernelGGL(k_obs_partial<float>, dim3(RED_BLOCKS), dim3(256), 0, s,
+                       (const float*)pop, links, N, partials);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, RED_BLOCKS, 6, result);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Contact angle
+// phi scratch layout (doubles): [0, A) reference layer, [A, 2A) first fluid
+// layer, [2A, 2A + nz) column, A = nx * ny.  Wall nodes hold 0.
+template <typename real>
+__global__ void k_ca_phi(const real* __restrict__ pop, const uint32_t* __restrict__ links, int nx,
+                         int ny, int nz, CaDev c, double* __restrict__ phi) {
+  const int A = nx * ny, N = A * nz;
+  const int total = 2 * A + nz;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    int x, y, z;
+    if (t < A) { x = t % nx; y = t / nx; z = c.zs + c.off; }
+    else if (t < 2 * A) { x = (t - A) % nx; y = (t - A) / nx; z = c.zs + 1; }
+    else { x = c.ic; y = c.jc; z = t - 2 * A; }
+    double v = 0;
+    if (z >= 0 && z < nz) {
+      const int i = (z * ny + y) * nx + x;
+      if (!(links[i] & SELF_SOLID)) {
+        double ra = 0, rb = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          ra += (double)pop[(size_t)k * N + i];
+          rb += (double)pop[(size_t)(Q + k) * N + i];
+        }
+        v = ra - rb;  // order parameter (Sec. 2)
+      }
+    }
+    phi[t] = v;
+  }
+}
+
+__device__ __forceinline__ double smoothstep(double t) {
+  return t <= 0.0 ? 0.0 : (t >= 1.0 ? 1.0 : t * t * (3.0 - 2.0 * t));
+}
+__device__ __forceinline__ double dsmoothstep(double t) {
+  return (t <= 0.0 || t >= 1.0) ? 0.0 : 6.0 * t * (1.0 - t);
+}
+
+struct CaGeom {
+  int nx, ny, nz;
+  const uint32_t* links;
+  CaDev c;
+  __device__ bool solid(int x, int y, int z) const {
+    if (z < 0 || z >= nz) return true;
+    return links[(z * ny + y) * nx + x] & SELF_SOLID;
+  }
+};
+
+// first crossing > 0 -> <= 0 of the column above k0, NaN if none
+__device__ double col_crossing(const CaGeom& g, const double* col, int k0) {
+  for (int k = k0; k + 1 < g.nz; ++k) {
+    if (g.solid(g.c.ic, g.c.jc, k + 1)) break;
+    const double p0 = col[k], p1 = col[k + 1];
+    if (p0 > 0.0 && p1 <= 0.0) return k + p0 / (p0 - p1);
+  }
+  return __builtin_nan("");
+}
+
+__device__ double layer_ray(const CaGeom& g, const double* layer, int sx, int sy, int* flags) {
+  const int len = sx != 0 ? g.nx : g.ny;
+  for (int m = 0; m < len / 2; ++m) {
+    const int x0 = wrap_index(g.c.ic + m * sx, g.nx), y0 = wrap_index(g.c.jc + m * sy, g.ny);
+    const int x1 = wrap_index(g.c.ic + (m + 1) * sx, g.nx);
+    const int y1 = wrap_index(g.c.jc + (m + 1) * sy, g.ny);
+    const double p0 = layer[y0 * g.nx + x0], p1 = layer[y1 * g.nx + x1];
+    if (p0 > 0.0 && p1 <= 0.0) return m + p0 / (p0 - p1);
+  }
+  *flags |= 8;  // SCD_CA_RAY_LIMIT
+  return (double)(len / 2);
+}
+
+__device__ double mean_ray(const CaGeom& g, const double* layer, int* flags) {
+  return 0.25 * (layer_ray(g, layer, 1, 0, flags) + layer_ray(g, layer, -1, 0, flags) +
+                 layer_ray(g, layer, 0, 1, flags) + layer_ray(g, layer, 0, -1, flags));
+}
+
+constexpr double RAD2DEG = 57.295779513082320876798154814105;
+
+// sphere through the reference circle (aref2 = aref^2) and the apex H above
+// it; base half-width at the wall from the cap height h
+__device__ double cap_theta(double aref2, double H, double h, double* R, double* a, int* flat) {
+  *R = (aref2 + H * H) / (2.0 * H);
+  const double a2 = 2.0 * (*R) * h - h * h;
+  if (!(a2 > 0.0)) { *flat = 1; *a = 0.0; return 180.0; }
+  *flat = 0;
+  *a = sqrt(a2);
+  return 2.0 * atan2(h, *a) * RAD2DEG;
+}
+
+// result slots
+enum {
+  R_TH1 = 0, R_H1, R_A1, R_R1, R_AREF1, R_BH1,
+  R_TH2, R_H2, R_A2, R_R2, R_AREF2, R_BH2,
+  R_CX, R_CY, R_FLAGS, R_STATUS, R_DTH_DH, R_DTH_DA, R_KEND
+};
+
+__global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ links, int nx,
+                                                   int ny, int nz, CaDev c,
+                                                   const double* __restrict__ phi,
+                                                   double* __restrict__ res) {
+  __shared__ double sh[4 * 16];
+  const CaGeom g{nx, ny, nz, links, c};
+  const int A = nx * ny;
+  const int kref = c.zs + c.off;
+  const double* ref = phi;
+  const double* low = phi + A;
+  const double* col = phi + 2 * A;
+  // layer sums: sum chi, centroid of phi > 0
+  double v[4] = {0, 0, 0, 0};
+  for (int t = threadIdx.x; t < A; t += blockDim.x) {
+    const int x = t % nx, y = t / nx;
+    if (g.solid(x, y, kref)) continue;
+    v[0] += smoothstep((ref[t] + c.eps) / (2.0 * c.eps));
+    if (ref[t] > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x != 0) return;
+
+  const double nan = __builtin_nan("");
+  int flags = 0;
+  double out[R_KEND + 1];
+  for (int j = 0; j <= R_KEND; ++j) out[j] = 0.0;
+  out[R_CX] = v[3] > 0.0 ? v[1] / v[3] : nan;
+  out[R_CY] = v[3] > 0.0 ? v[2] / v[3] : nan;
+  const double zw = c.zs + 0.5, d = kref - zw;
+  double status = 0.0;
+  if (!(col[c.zs + 1] > 0.0)) {
+    flags |= 32;  // SCD_CA_NO_DROP
+    out[R_TH1] = out[R_TH2] = nan;
+    status = -4.0;
+  } else {
+    int flat = 0;
+    if (col[kref] > 0.0) {
+      const double ztop = col_crossing(g, col, kref);
+      if (isnan(ztop)) {
+        flags |= 16;
+        out[R_TH1] = nan;
+      } else {
+        const double h = ztop - zw, H = ztop - kref;
+        const double aref = mean_ray(g, ref, &flags);
+        double R, a;
+        out[R_TH1] = cap_theta(aref * aref, H, h, &R, &a, &flat);
+        if (flat) flags |= 2;
+        out[R_H1] = h; out[R_BH1] = H; out[R_AREF1] = aref; out[R_R1] = R; out[R_A1] = a;
+      }
+    } else {
+      flags |= 1;  // SCD_CA_NO_REF
+      const double ztop = col_crossing(g, col, c.zs + 1);
+      if (isnan(ztop)) {
+        flags |= 16;
+        out[R_TH1] = nan;
+      } else {
+        const double h = ztop - zw;
+        const double a = mean_ray(g, low, &flags);
+        out[R_TH1] = 2.0 * atan2(h, a) * RAD2DEG;
+        out[R_H1] = h; out[R_A1] = a; out[R_BH1] = ztop - kref; out[R_AREF1] = nan;
+        out[R_R1] = (a * a + h * h) / (2.0 * h);
+      }
+    }
+    // E2
+    auto chi = [&](int k) {
+      if (g.solid(c.ic, c.jc, k)) return 0.0;
+      return smoothstep((col[k] + c.eps) / (2.0 * c.eps));
+    };
+    int kend = kref + 1;
+    while (kend < nz && chi(kend) > 0.0) ++kend;
+    double H = 0.5 * chi(kref);
+    for (int k = kref + 1; k < kend; ++k) H += chi(k);
+    const double Aref = v[0] / M_PI;
+    out[R_BH2] = H;
+    out[R_AREF2] = sqrt(Aref);
+    out[R_KEND] = kend;
+    if (!(H > 0.0)) {
+      flags |= 64;
+      out[R_TH2] = nan;
+    } else {
+      const double h = H + d;
+      double R, a;
+      out[R_TH2] = cap_theta(Aref, H, h, &R, &a, &flat);
+      if (flat) flags |= 4;
+      out[R_H2] = h; out[R_R2] = R; out[R_A2] = a;
+      if (!flat) {
+        // partial derivatives of theta_E2 (radians) with respect to H and to
+        // Aref = aref^2, from a^2 = (Aref + H^2) h / H - h^2, h = H + d
+        const double a2 = a * a;
+        const double da2_dA = h / H;
+        const double da2_dH =
+            ((2.0 * H * h + (Aref + H * H)) * H - (Aref + H * H) * h) / (H * H) - 2.0 * h;
+        const double den = a2 + h * h;
+        out[R_DTH_DH] = 2.0 * (a - h * da2_dH / (2.0 * a)) / den;
+        out[R_DTH_DA] = 2.0 * (-h * da2_dA / (2.0 * a)) / den;
+      }
+    }
+  }
+  out[R_FLAGS] = flags;
+  out[R_STATUS] = status;
+  for (int j = 0; j <= R_KEND; ++j) res[j] = out[j];
+}
+
+hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                                int nz, CaDev cfg, double* phi_scratch, double* result,
+                                hipStream_t s) {
+  const int total = 2 * nx * ny + nz;
+  const int blocks = (total + 255) / 256;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_ca_phi<double>, dim3(blocks), dim3(256), 0, s, (const double*)pop, links,
+                       nx, ny, nz, cfg, phi_scratch);
+  else
+    hipLaunchKernelGGL(k_ca_phi<float>, dim3(blocks), dim3(256), 0, s, (const float*)pop, links,
+                       nx, ny, nz, cfg, phi_scratch);
+  hipLaunchKernelGGL(k_ca_finish, dim3(1), dim3(256), 0, s, links, nx, ny, nz, cfg, phi_scratch,
+                     result);
+  return hipGetLastError();
+}
+
+// Seed of the adjoint: lambda_k^A = dL/dtheta * dtheta/dphi, lambda_k^B =
+// -lambda_k^A at every node of the reference layer and of the column run of
+// the droplet above it (all other entries are zeroed beforehand).
+template <typename real>
+__global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, int nz, CaDev c,
+                          const double* __restrict__ phi, const double* __restrict__ res,
+                          double dL, real* __restrict__ lam) {
+  const int A = nx * ny, N = A * nz;
+  const int kref = c.zs + c.off;
+  const int kend = (int)res[R_KEND];
+  const double dH = res[R_DTH_DH], dA = res[R_DTH_DA];
+  const int total = A + nz;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    int x, y, z;
+    double p;
+    if (t < A) { x = t % nx; y = t / nx; z = kref; p = phi[t]; }
+    else { x = c.ic; y = c.jc; z = t - A; p = phi[2 * A + z]; if (z <= kref || z >= kend) continue; }
+    const int i = (z * ny + y) * nx + x;
+    if (links[i] & SELF_SOLID) continue;
+    const double dchi = dsmoothstep((p + c.eps) / (2.0 * c.eps)) / (2.0 * c.eps);
+    double gr;
+    if (t < A) {
+      gr = dA * dchi / M_PI;
+      if (x == c.ic && y == c.jc) gr += 0.5 * dH * dchi;
+    } else {
+      gr = dH * dchi;
+    }
+    const real va = (real)(dL * gr), vb = (real)(-dL * gr);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      lam[(size_t)k * N + i] = va;
+      lam[(size_t)(Q + k) * N + i] = vb;
+    }
+  }
+}
+
+hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,
+                          const double* phi_scratch, const double* result, double dL_dtheta,
+                          void* lambda, hipStream_t s) {
+  const size_t N = (size_t)nx * ny * nz;
+  hipError_t e = launch_fill(dtype, lambda, 2 * Q * N, 0.0, s);
+  if (e != hipSuccess) return e;
+  const int total = nx * ny + nz;
+  const int blocks = (total + 255) / 256;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_ca_seed<double>, dim3(blocks), dim3(256), 0, s, links, nx, ny, nz, cfg,
+                       phi_scratch, result, dL_dtheta, (double*)lambda);
+  else
+    hipLaunchKernelGGL(k_ca_seed<float>, dim3(blocks), dim3(256), 0, s, links, nx, ny, nz, cfg,
+                       phi_scratch, result, dL_dtheta, (float*)lambda);
+  return hipGetLastError();
+}
+
+}  // namespace scd

@@ -1,0 +1,553 @@
+// step.hip -- the fused time step of the two-component Shan-Chen D3Q19 model
+// with interacting walls (Sec. 2 of the paper) on gfx950, plus the small
+// kernels around it (link masks, initial equilibrium, densities).
+//
+// Fused step, one z-marching tile per workgroup:
+//   * a workgroup owns TX x TY columns and a chunk [za, zb) of z planes;
+//   * for every plane p it pulls the 38 post-stream populations of its
+//     columns (streaming + mid-grid bounce-back), computes the densities and
+//     the pseudopotential products e^a = G^a psi^b that the force stencil
+//     needs, and writes them into a ring of 4 planes in LDS; the ring also
+//     holds a one-node halo around the tile, whose densities are pulled by
+//     spare threads (those reads are served by L2 since the neighbouring
+//     tiles read the same lines);
+//   * one barrier later plane p - 1 has e on planes p - 2, p - 1, p and is
+//     collided: 18-neighbour Shan-Chen + wall force, the common velocity and
+//     the velocity shift, BGK toward the third-order equilibrium, and 38
+//     coalesced stores.  The pulled populations of p - 1 stay in registers.
+// HBM traffic per fluid node and step is one read and one write of each
+// population (plus a 4-byte link mask); everything else is on chip.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace scd {
+
+template <typename real>
+struct alignas(2 * sizeof(real)) E2 {
+  real a, b;  // e^A = G^A psi^B and e^B = G^B psi^A at one node
+};
+
+template <int TX, int TY>
+struct Tile {
+  static constexpr int NT = TX * TY;
+  static constexpr int LX = TX + 2;
+  static constexpr int LY = TY + 2;
+  static constexpr int P = LX * LY;          // LDS positions per plane
+  static constexpr int R = 2 * LX + 2 * TY;  // halo positions per plane
+  static constexpr int HPT = (R + NT - 1) / NT;
+};
+
+// e^A, e^B of a fluid node from its post-stream densities (Eq. SCforce:
+// the neighbour's psi of the *other* species times the coupling).
+template <typename real>
+__device__ __forceinline__ E2<real> fluid_e(const Phys<real>& ph, real ra, real rb) {
+  E2<real> e;
+  e.a = ph.gab * psi_of(ph.psi_form, rb);
+  e.b = ph.gab * psi_of(ph.psi_form, ra);
+  return e;
+}
+// wall node: constant content, coupling g_wall^a (Sec. 2 wall model)
+template <typename real>
+__device__ __forceinline__ E2<real> wall_e(const Phys<real>& ph) {
+  E2<real> e;
+  e.a = ph.gw[0] * ph.psiw[1];
+  e.b = ph.gw[1] * ph.psiw[0];
+  return e;
+}
+
+// Eq. (SCforce) sums of one node from the e values of its 18 neighbours
+// (read through the three plane pointers of the LDS ring):
+// S^a = sum_k W_k e^a(x + c_k) c_k.
+template <typename real, int LX>
+__device__ __forceinline__ void force_sums(const Phys<real>& ph, const E2<real>* __restrict__ sm,
+                                           const E2<real>* __restrict__ s0,
+                                           const E2<real>* __restrict__ sp, int pos,
+                                           real (&S)[6]) {
+  real sax = 0, say = 0, saz = 0, sbx = 0, sby = 0, sbz = 0;
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    const E2<real>* s = CZ[k] < 0 ? sm : (CZ[k] > 0 ? sp : s0);
+    E2<real> e = s[pos + CY[k] * LX + CX[k]];
+    real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+    real wa = w * e.a, wb = w * e.b;
+    if (CX[k]) { sax += CX[k] * wa; sbx += CX[k] * wb; }
+    if (CY[k]) { say += CY[k] * wa; sby += CY[k] * wb; }
+    if (CZ[k]) { saz += CZ[k] * wa; sbz += CZ[k] * wb; }
+  }
+  S[0] = sax; S[1] = say; S[2] = saz; S[3] = sbx; S[4] = sby; S[5] = sbz;
+}
+
+// Keeps the compiler from moving instructions across this point, so that
+// the phases of a node update do not all hold their registers at once.
+__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Collision of one fluid node given its post-stream populations n and the
+// force sums S of Eq. (SCforce).
+template <typename real>
+__device__ __forceinline__ void collide_node(const LatDev<real>& L, const real (&n)[38],
+                                             const real (&Sf)[6], int i) {
+  const Phys<real>& ph = L.ph;
+  real ra, jax, jay, jaz, rb, jbx, jby, jbz;
+  moments(&n[0], ra, jax, jay, jaz);
+  moments(&n[Q], rb, jbx, jby, jbz);
+  const real sax = Sf[0], say = Sf[1], saz = Sf[2], sbx = Sf[3], sby = Sf[4], sbz = Sf[5];
+  const real pa = psi_of(ph.psi_form, ra), pb = psi_of(ph.psi_form, rb);
+  const real fax = -pa * sax, fay = -pa * say, faz = -pa * saz;
+  const real fbx = -pb * sbx, fby = -pb * sby, fbz = -pb * sbz;
+  // common velocity u' = sum_a j^a / tau^a / sum_a rho^a / tau^a, then the
+  // velocity shift u^a = u' + tau^a F^a / rho^a (Sec. 2)
+  const real itA = ph.inv_tau[0], itB = ph.inv_tau[1];
+  const real iR = real(1) / (ra * itA + rb * itB);
+  const real upx = (jax * itA + jbx * itB) * iR;
+  const real upy = (jay * itA + jby * itB) * iR;
+  const real upz = (jaz * itA + jbz * itB) * iR;
+  const real sA = ph.tau[0] / ra, sB = ph.tau[1] / rb;
+  real u[2][3] = {{upx + sA * fax, upy + sA * fay, upz + sA * faz},
+                  {upx + sB * fbx, upy + sB * fby, upz + sB * fbz}};
+  const real rho[2] = {ra, rb};
+  constexpr uint32_t S = sizeof(real);
+  const uint32_t N = (uint32_t)L.N;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const real ux = u[a][0], uy = u[a][1], uz = u[a][2];
+    const real uu = ux * ux + uy * uy + uz * uz;
+    const real it = ph.inv_tau[a];
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * L.N);
+    real moving = 0;  // sum of the 18 moving equilibria
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const int o = k + 1;  // OPP[k] for odd k
+      real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+      real fk, fo;
+      equilibrium_pair(real(WEIGHT[k]) * rho[a], s, uu, fk, fo);
+      moving += fk + fo;
+      real nk = n[a * Q + k], no = n[a * Q + o];
+      st_off<real>(out, ((uint32_t)k * N + (uint32_t)i) * S, nk + (fk - nk) * it);
+      st_off<real>(out, ((uint32_t)o * N + (uint32_t)i) * S, no + (fo - no) * it);
+    }
+    // rest population: the equilibrium's zeroth moment is rho exactly, so
+    // n^eq_0 = rho - sum of the moving ones (the same value as
+    // zeta_0 rho (1 - 3/2 u^2) in exact arithmetic, and mass-exact in
+    // floating point where the weights 1/3, 1/18, 1/36 are not)
+    const real eq0 = rho[a] - moving;
+    const real f0 = n[a * Q];
+    st_off<real>(out, (uint32_t)i * S, f0 + (eq0 - f0) * it);
+  }
+}
+
+// Variants of the z-march:
+//   REG    -- the pulled populations of the plane being collided stay in
+//             registers while the next plane is pulled (two sets live);
+//   REPULL -- the look-ahead plane is pulled for its densities only and the
+//             collided plane is pulled again (from L2 / the last-level
+//             cache): one set live, so more waves fit on a SIMD.
+constexpr int VAR_REG = 0;
+constexpr int VAR_REPULL = 1;
+
+// One z-marching tile of the fused step (shared by the single-lattice and
+// the batched kernels).  lds: 4 * Tile::P entries.
+template <typename real, int TX, int TY, int VAR>
+__device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by, int za, int zb,
+                                          E2<real>* __restrict__ lds) {
+  using T = Tile<TX, TY>;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int x0 = bx * TX, y0 = by * TY;
+  const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  int xs[3], ys[3];
+  axis3(wrap_index(x0 + tx, nx), nx, xs);
+  axis3(wrap_index(y0 + ty, ny), ny, ys);
+  const int pos = (ty + 1) * T::LX + (tx + 1);
+
+  // halo positions served by this thread
+  int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT];
+  bool hval[T::HPT];
+  // halo positions are dealt out lane-major over all waves, so every wave
+  // pulls about the same number of halo nodes per plane (the per-plane
+  // barrier waits for the slowest wave)
+  constexpr int HW = T::HPT * T::NT / 64;  // waves that take halo slots
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) {
+    const int slot = tid + h * T::NT;
+    int q = (slot & 63) * HW + (slot >> 6);
+    hval[h] = q < T::R;
+    int lx, ly;
+    if (q < T::LX) { ly = -1; lx = q - 1; }
+    else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
+    else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
+    else { lx = TX; ly = q - 2 * T::LX - TY; }
+    if (!hval[h]) { lx = 0; ly = 0; }
+    axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
+    axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
+    hpos[h] = (ly + 1) * T::LX + (lx + 1);
+  }
+
+  const E2<real> ewall = wall_e(L.ph);
+  real ncur[38], nnext[38];
+  bool solid_cur = true, solid_next = true;
+
+  // e of plane zr (raw, may lie outside [0, nz)) into ring slot zr & 3; the
+  // interior populations are kept in nout when keep is set.
+  auto plane = [&](int zr, bool keep, real(&nout)[38], bool& solid_out) {
+    int zs[3];
+    axis3(wrap_index(zr, nz), nz, zs);
+    E2<real>* slot = lds + (zr & 3) * T::P;
+    {
+      const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+      const uint32_t lb = L.links[i];
+      E2<real> e;
+      solid_out = (lb & SELF_SOLID) != 0;
+      if (solid_out) {
+        e = ewall;
+      } else if (keep) {
+        pull38(L.src, N, i, xs, ys, zs, nx, ny, lb, nout);
+        real ra = 0, rb = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) { ra += nout[k]; rb += nout[Q + k]; }
+        e = fluid_e(L.ph, ra, rb);
+      } else {
+        real ra, rb;
+        pull_density(L.src, N, i, xs, ys, zs, nx, ny, lb, ra, rb);
+        e = fluid_e(L.ph, ra, rb);
+      }
+      slot[pos] = e;
+    }
+    if (VAR == VAR_REPULL) phase_fence();
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      const uint32_t lb = L.links[i];
+      E2<real> e;
+      if (lb & SELF_SOLID) {
+        e = ewall;
+      } else {
+        real ra, rb;
+        pull_density(L.src, N, i, hx[h], hy[h], zs, nx, ny, lb, ra, rb);
+        e = fluid_e(L.ph, ra, rb);
+      }
+      slot[hpos[h]] = e;
+    }
+  };
+
+  if constexpr (VAR == VAR_REG) {
+    plane(za - 1, false, nnext, solid_next);
+    plane(za, true, ncur, solid_cur);
+    for (int p = za + 1; p <= zb; ++p) {
+      plane(p, p < zb, nnext, solid_next);
+      __syncthreads();
+      const int zc = p - 1;
+      if (active && !solid_cur) {
+        const int i = (zc * ny + ys[1]) * nx + xs[1];
+        real S[6];
+        force_sums<real, T::LX>(L.ph, lds + ((zc - 1) & 3) * T::P, lds + (zc & 3) * T::P,
+                                lds + ((zc + 1) & 3) * T::P, pos, S);
+        collide_node<real>(L, ncur, S, i);
+      }
+#pragma unroll
+      for (int k = 0; k < 38; ++k) ncur[k] = nnext[k];
+      solid_cur = solid_next;
+    }
+  } else {
+    plane(za - 1, false, nnext, solid_next);
+    plane(za, false, nnext, solid_next);
+    for (int p = za + 1; p <= zb; ++p) {
+      plane(p, false, nnext, solid_next);
+      __syncthreads();
+      const int zc = p - 1;
+      if (active) {
+        int zs[3];
+        axis3(zc, nz, zs);
+        const int i = (zc * ny + ys[1]) * nx + xs[1];
+        const uint32_t lb = L.links[i];
+        if (!(lb & SELF_SOLID)) {
+          real S[6];
+          force_sums<real, T::LX>(L.ph, lds + ((zc - 1) & 3) * T::P, lds + (zc & 3) * T::P,
+                                  lds + ((zc + 1) & 3) * T::P, pos, S);
+          phase_fence();
+          pull38(L.src, N, i, xs, ys, zs, nx, ny, lb, ncur);
+          collide_node<real>(L, ncur, S, i);
+        }
+      }
+    }
+  }
+}
+
+// Map the hardware block id to a tile.  Workgroups are handed to the 8 XCDs
+// round-robin; with remap each XCD receives one contiguous range of tiles
+// (x fastest, then y, then z-chunk), so neighbouring tiles that share halo
+// lines and chunk-boundary planes share that XCD's L2.
+__device__ __forceinline__ bool tile_of_block(int b, int total, int remap, int gx, int gy, int& bx,
+                                              int& by, int& bz) {
+  if (remap) {
+    int per = (total + 7) / 8;
+    b = (b & 7) * per + (b >> 3);
+    if (b >= total) return false;
+  }
+  bx = b % gx;
+  by = (b / gx) % gy;
+  bz = b / (gx * gy);
+  return true;
+}
+
+template <typename real, int TX, int TY, int VAR, int WPE>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+void k_step(LatDev<real> L, int gx, int gy, int nchunks, int zc, int remap) {
+  __shared__ E2<real> lds[4 * Tile<TX, TY>::P];
+  int bx, by, bz;
+  if (!tile_of_block(blockIdx.x, gx * gy * nchunks, remap, gx, gy, bx, by, bz)) return;
+  const int za = bz * zc;
+  const int zb = min(za + zc, L.nz);
+  step_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds);
+}
+
+// Batched: a persistent grid walks a list of (lattice, tile) items.
+template <typename real, int TX, int TY, int VAR, int WPE>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+void k_step_batch(const LatDev<real>* __restrict__ lats, const int4* __restrict__ items,
+                  int nitems) {
+  __shared__ E2<real> lds[4 * Tile<TX, TY>::P];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];  // lattice, bx, by, (z-chunk << 16) | first plane
+    const LatDev<real> L = lats[w.x];
+    const int zc = w.w >> 16, za = w.w & 0xffff;
+    step_tile<real, TX, TY, VAR>(L, w.y, w.z, za, min(za + zc, L.nz), lds);
+    __syncthreads();  // the next item rewrites the LDS ring
+  }
+}
+
+// ----------------------------------------------------------------------------
+__global__ void k_links(const uint8_t* __restrict__ solid, uint32_t* __restrict__ links, int nx,
+                        int ny, int nz) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    int xs[3], ys[3], zs[3];
+    axis3(x, nx, xs);
+    axis3(y, ny, ys);
+    axis3(z, nz, zs);
+    uint32_t lb = solid[i] ? SELF_SOLID : 0u;
+#pragma unroll
+    for (int k = 1; k < Q; ++k)
+      if (solid[nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k])]) lb |= 1u << k;
+    links[i] = lb;
+  }
+}
+
+// Sec. 2 initial state: fluid at rest, C_k = zeta_k rho.
+template <typename real>
+__global__ void k_init(real* __restrict__ pop, const double* __restrict__ ra,
+                       const double* __restrict__ rb, const uint32_t* __restrict__ links, int N) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const bool solid = links[i] & SELF_SOLID;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      pop[(size_t)k * N + i] = solid ? real(0) : real(WEIGHT[k] * ra[i]);
+      pop[(size_t)(Q + k) * N + i] = solid ? real(0) : real(WEIGHT[k] * rb[i]);
+    }
+  }
+}
+
+// rho^a = sum_k C_k^a of the stored state, FP64 output rho[a * N + i].
+template <typename real>
+__global__ void k_density(const real* __restrict__ pop, const uint32_t* __restrict__ links,
+                          double* __restrict__ rho, int N) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    double ra = 0, rb = 0;
+    if (!(links[i] & SELF_SOLID)) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        ra += (double)pop[(size_t)k * N + i];
+        rb += (double)pop[(size_t)(Q + k) * N + i];
+      }
+    }
+    rho[i] = ra;
+    rho[(size_t)N + i] = rb;
+  }
+}
+
+// Post-stream densities of every fluid node (0 at wall nodes), rho[a*N + i].
+template <typename real>
+__global__ void k_stream_density(const real* __restrict__ pop, const uint32_t* __restrict__ links,
+                                 real* __restrict__ rho, int nx, int ny, int nz) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    real ra = 0, rb = 0;
+    if (!(lb & SELF_SOLID)) {
+      int xs[3], ys[3], zs[3];
+      axis3(i % nx, nx, xs);
+      axis3((i / nx) % ny, ny, ys);
+      axis3(i / (nx * ny), nz, zs);
+      pull_density(pop, N, i, xs, ys, zs, nx, ny, lb, ra, rb);
+    }
+    rho[i] = ra;
+    rho[(size_t)N + i] = rb;
+  }
+}
+
+template <typename real>
+__global__ void k_fill(real* __restrict__ p, size_t n, real v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ----------------------------------------------------------------------------
+// Host launchers
+static int grid_for(size_t n, int block) {
+  size_t g = (n + block - 1) / block;
+  return (int)(g > 8192 ? 8192 : (g < 1 ? 1 : g));
+}
+
+hipError_t launch_links(const uint8_t* solid, uint32_t* links, int nx, int ny, int nz,
+                        hipStream_t s) {
+  size_t N = (size_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_links, dim3(grid_for(N, 256)), dim3(256), 0, s, solid, links, nx, ny, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int dtype, void* pop, const double* ra, const double* rb,
+                       const uint32_t* links, int N, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_init<double>, dim3(grid_for(N, 256)), dim3(256), 0, s, (double*)pop, ra,
+                       rb, links, N);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(grid_for(N, 256)), dim3(256), 0, s, (float*)pop, ra, rb,
+                       links, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int N,
+                          hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_density<double>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                       (const double*)pop, links, rho, N);
+  else
+    hipLaunchKernelGGL(k_density<float>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                       (const float*)pop, links, rho, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_density(int dtype, const void* pop, const uint32_t* links, void* rho,
+                                 int nx, int ny, int nz, hipStream_t s) {
+  size_t N = (size_t)nx * ny * nz;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_stream_density<double>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                       (const double*)pop, links, (double*)rho, nx, ny, nz);
+  else
+    hipLaunchKernelGGL(k_stream_density<float>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                       (const float*)pop, links, (float*)rho, nx, ny, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, (double*)p, n, v);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, (float*)p, n,
+                       (float)v);
+  return hipGetLastError();
+}
+
+// Compiled variants (tx, ty, var, wpe): tile shape, z-march variant and
+// the minimum waves per SIMD the register allocation must allow.
+#define SCD_VARIANTS(X)                                                                   \
+  X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 0, 2) X(32, 8, 0, 2) X(32, 4, 0, 2) X(64, 2, 0, 2) \
+  X(64, 4, 0, 3) X(64, 4, 1, 1) X(32, 8, 1, 1) X(64, 8, 1, 2) X(16, 16, 1, 2) X(64, 4, 1, 4)
+
+static const int kVariants[][4] = {
+#define SCD_ROW(a, b, v, w) {a, b, v, w},
+    SCD_VARIANTS(SCD_ROW)
+#undef SCD_ROW
+};
+
+int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+void variant_at(int i, int* tx, int* ty, int* var, int* wpe) {
+  *tx = kVariants[i][0];
+  *ty = kVariants[i][1];
+  *var = kVariants[i][2];
+  *wpe = kVariants[i][3];
+}
+int variant_find(int tx, int ty, int var, int wpe) {
+  for (int i = 0; i < variant_count(); ++i)
+    if (kVariants[i][0] == tx && kVariants[i][1] == ty && kVariants[i][2] == var &&
+        kVariants[i][3] == wpe)
+      return i;
+  return -1;
+}
+
+template <typename real>
+static hipError_t launch_step_t(const LatDev<real>& L, int variant, int zc, int remap,
+                                hipStream_t s) {
+  if (variant < 0 || variant >= variant_count()) return hipErrorInvalidValue;
+  const int tx = kVariants[variant][0], ty = kVariants[variant][1];
+  const int var = kVariants[variant][2], wpe = kVariants[variant][3];
+  const int gx = (L.nx + tx - 1) / tx, gy = (L.ny + ty - 1) / ty;
+  const int nch = (L.nz + zc - 1) / zc;
+  const int total = gx * gy * nch;
+  const int blocks = remap ? ((total + 7) / 8) * 8 : total;
+#define SCD_LAUNCH(a, b, v, w)                                                              \
+  if (tx == a && ty == b && var == v && wpe == w) {                                         \
+    hipLaunchKernelGGL((k_step<real, a, b, v, w>), dim3(blocks), dim3(a * b), 0, s, L, gx, gy, \
+                       nch, zc, remap);                                                     \
+    return hipGetLastError();                                                               \
+  }
+  SCD_VARIANTS(SCD_LAUNCH)
+#undef SCD_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* links, int nx,
+                       int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
+                       hipStream_t s) {
+  if (dtype == 0) {
+    LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
+                     phys_cast<double>(ph)};
+    return launch_step_t(L, variant, zc, remap, s);
+  }
+  LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
+                  phys_cast<float>(ph)};
+  return launch_step_t(L, variant, zc, remap, s);
+}
+
+template <typename real>
+static hipError_t launch_batch_t(const void* lats, const void* items, int nitems, int grid,
+                                 int variant, hipStream_t s) {
+  if (variant < 0 || variant >= variant_count()) return hipErrorInvalidValue;
+  const int tx = kVariants[variant][0], ty = kVariants[variant][1];
+  const int var = kVariants[variant][2], wpe = kVariants[variant][3];
+#define SCD_LAUNCHB(a, b, v, w)                                                                 \
+  if (tx == a && ty == b && var == v && wpe == w) {                                             \
+    hipLaunchKernelGGL((k_step_batch<real, a, b, v, w>), dim3(grid), dim3(a * b), 0, s,         \
+                       (const LatDev<real>*)lats, (const int4*)items, nitems);                  \
+    return hipGetLastError();                                                                   \
+  }
+  SCD_VARIANTS(SCD_LAUNCHB)
+#undef SCD_LAUNCHB
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
+                             int variant, hipStream_t s) {
+  if (dtype == 0) return launch_batch_t<double>(lats, items, nitems, grid, variant, s);
+  return launch_batch_t<float>(lats, items, nitems, grid, variant, s);
+}
+
+size_t latdev_size(int dtype) { return dtype == 0 ? sizeof(LatDev<double>) : sizeof(LatDev<float>); }
+
+void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_t* links, int nx,
+                 int ny, int nz, const PhysD& ph) {
+  if (dtype == 0) {
+    LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
+                     phys_cast<double>(ph)};
+    *(LatDev<double>*)out = L;
+  } else {
+    LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
+                    phys_cast<float>(ph)};
+    *(LatDev<float>*)out = L;
+  }
+}
+
+}  // namespace scd

@@ -1,0 +1,73 @@
+"""torch.autograd.Function over the library's checkpointed adjoint driver.
+
+Forward: scd_ckpt_forward runs the lattice from the initial densities,
+storing the state every ``ckpt_every`` steps, and returns the loss
+(theta_E2 - target)^2 in deg^2.  Backward: scd_ckpt_backward recomputes each
+segment from its checkpoint and runs the hand-written adjoint steps in
+reverse, giving dL/d(rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B).
+"""
+import ctypes
+
+import torch
+
+from . import binding as B
+
+
+class GradSetup:
+    """Buffers and settings of one differentiable run (caller keeps it alive)."""
+
+    def __init__(self, params, solid, rho_a, rho_b, nsteps, ckpt_every, ca_cfg, target_deg,
+                 device="cuda", stream=None):
+        self.lat = B.Lattice(params, solid, device=device, adjoint=True, stream=stream)
+        self.params = dict(params)
+        self.nsteps = int(nsteps)
+        self.K = int(ckpt_every)
+        self.cfg = B.make_ca_cfg(ca_cfg)
+        self.target = float(target_deg)
+        dev = self.lat.device
+        self.rho_a = B._device_f64(rho_a, dev).reshape(-1)
+        self.rho_b = B._device_f64(rho_b, dev).reshape(-1)
+        nseg = (self.nsteps + self.K - 1) // self.K
+        shape = (2, 19) + self.lat.shape
+        dt = self.lat.dtype
+        self.ckpt = torch.empty((nseg,) + shape, dtype=dt, device=dev)
+        self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
+        self.lam = torch.empty((2,) + shape, dtype=dt, device=dev)
+        self.theta = float("nan")
+
+    def apply_params(self, values):
+        v = [float(x) for x in values]
+        p = dict(self.params, rho_wall=(v[0], v[1]), g_ab=v[2], g_wall=(v[3], v[4]))
+        self.lat.set_params(p)
+        self.params = p
+
+    def forward(self):
+        self.lat._after_torch()
+        out = (ctypes.c_double * 2)()
+        B.check(B.lib().scd_ckpt_forward(self.lat.h, B._ptr(self.rho_a), B._ptr(self.rho_b), self.nsteps,
+                                         self.K, B._ptr(self.ckpt), ctypes.byref(self.cfg), self.target, out))
+        self.theta = out[1]
+        return out[0]
+
+    def backward(self):
+        g = (ctypes.c_double * 5)()
+        B.check(B.lib().scd_ckpt_backward(self.lat.h, self.nsteps, self.K, B._ptr(self.ckpt), B._ptr(self.seg),
+                                          B._ptr(self.lam), ctypes.byref(self.cfg), self.target, g))
+        return list(g)
+
+
+class ContactAngleFn(torch.autograd.Function):
+    """loss = ContactAngleFn.apply(wall, setup) with wall = tensor of
+    (rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B) (float64, CPU)."""
+
+    @staticmethod
+    def forward(ctx, wall, setup):
+        setup.apply_params(wall.detach().cpu().tolist())
+        loss = setup.forward()
+        ctx.setup = setup
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.setup.backward()
+        return grad_out * torch.tensor(g, dtype=torch.float64), None

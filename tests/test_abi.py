@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function that include/scdrop.h declares, and rejects bad parameters
+before touching the device."""
+import ctypes
+
+import pytest
+
+import paper_0910_3915_amd as scd
+from paper_0910_3915_amd import binding as B
+import workloads as W
+
+
+def test_library_exports_header_symbols():
+    L = scd.lib()
+    names = scd.header_symbols()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.scd_version()
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header's field lists (natural alignment)
+    assert ctypes.sizeof(B.ScdParams) == 6 * 4 + 9 * 8
+    assert ctypes.sizeof(B.ScdObs) == 5 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(B.ScdCaCfg) == 4 * 4 + 8
+    assert ctypes.sizeof(B.ScdCa) == 14 * 8 + 2 * 4
+
+
+def _sizes(p):
+    sp = B.make_params(p)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    return scd.lib().scd_sizes(ctypes.byref(sp), ctypes.byref(a), ctypes.byref(b)), a.value, b.value
+
+
+def test_sizes_and_validation():
+    st, pop, work = _sizes(W.params(32, 32, 32, 0.1))
+    assert st == 0 and pop == 2 * 19 * 32 ** 3 * 8 and work > 32 ** 3 * 4
+    st, pop32, _ = _sizes(W.params(32, 32, 32, 0.1, dtype="f32"))
+    assert st == 0 and pop32 == pop // 2
+    bad = [W.params(32, 32, 32, 0.1, tau=(0.5, 1.0)),
+           W.params(0, 32, 32, 0.1),
+           W.params(32, 32, 32, -0.1),
+           W.params(32, 32, 32, 0.1, rho_wall=(-0.1, 0.5)),
+           W.params(32, 32, 32, 0.1, g_wall=(0.1, float("nan"))),
+           dict(W.params(32, 32, 32, 0.1), psi=3)]
+    for p in bad:
+        st, _, _ = _sizes(p)
+        assert st == B.SCD_EINVAL, p
+        assert scd.lib().scd_last_error()
+
+
+def test_adjoint_flag_grows_work_area():
+    p = W.params(16, 16, 12, 0.1)
+    sp0, sp1 = B.make_params(p), B.make_params(p, adjoint=True)
+    a, w0, w1 = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    scd.lib().scd_sizes(ctypes.byref(sp0), ctypes.byref(a), ctypes.byref(w0))
+    scd.lib().scd_sizes(ctypes.byref(sp1), ctypes.byref(a), ctypes.byref(w1))
+    assert w1.value >= w0.value + 16 * 16 * 16 * 12 * 8
+
+
+def test_tile_list():
+    rows = scd.tile_list()
+    assert len(rows) >= 4 and all(len(r) == 4 for r in rows)
+    assert any(r[:2] == (64, 4) for r in rows)
+    assert scd.variant_index(*rows[1]) == 1
+
+
+def test_batch_sizes_reject_mixed_dtypes():
+    ps = (B.ScdParams * 2)(B.make_params(W.params(16, 16, 16, 0.1)),
+                           B.make_params(W.params(16, 16, 16, 0.1, dtype="f32")))
+    n = ctypes.c_size_t()
+    assert scd.lib().scd_batch_sizes(2, ps, ctypes.byref(n)) == B.SCD_EINVAL
