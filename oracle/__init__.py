@@ -22,6 +22,7 @@ CA_RAY_LIMIT = 8
 CA_NO_APEX = 16
 CA_NO_DROP = 32
 CA_E2_EMPTY = 64
+CA_E2_WHOLE_LAYER = 128
 
 
 class OraParams(ctypes.Structure):

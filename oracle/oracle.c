@@ -456,16 +456,51 @@ static int e2_column_end(const phi_view* v, const ora_ca_cfg* cfg) {
   return k;
 }
 
+/* Radius of the disk around the column over which E2 sums the reference
+ * layer: the largest E1 half-chord in that layer plus 4 lattice units (the
+ * indicator's transition band), so that other A-rich regions of the layer
+ * (a film on the wall, a second droplet) are not counted.  Without a droplet
+ * at the reference layer the whole layer is used (flag E2_WHOLE_LAYER). */
+static double e2_window(const phi_view* v, const ora_ca_cfg* cfg, int* flags) {
+  int kref = cfg->z_solid_top + cfg->offset;
+  if (!(phi_at(v, cfg->ic, cfg->jc, kref) > 0.0)) {
+    *flags |= ORA_CA_E2_WHOLE_LAYER;
+    return INFINITY;
+  }
+  int f = 0;
+  double r = half_chord(v, cfg->ic, cfg->jc, kref, 1, 0, &f);
+  double t = half_chord(v, cfg->ic, cfg->jc, kref, -1, 0, &f);
+  if (t > r) r = t;
+  t = half_chord(v, cfg->ic, cfg->jc, kref, 0, 1, &f);
+  if (t > r) r = t;
+  t = half_chord(v, cfg->ic, cfg->jc, kref, 0, -1, &f);
+  if (t > r) r = t;
+  return r + 4.0;
+}
+
+/* periodic (minimum image) distance along one axis */
+static int image_dist(int a, int b, int n) {
+  int d = a > b ? a - b : b - a;
+  return d < n - d ? d : n - d;
+}
+
+static int in_window(const phi_view* v, const ora_ca_cfg* cfg, double rcut, int x, int y) {
+  double dx = image_dist(x, cfg->ic, v->L->nx), dy = image_dist(y, cfg->jc, v->L->ny);
+  return dx * dx + dy * dy <= rcut * rcut;
+}
+
 /* E2 column and layer sums: H = 1/2 chi(kref) + sum_{kref < k < kend} chi
- * and A = sum over the reference layer of chi / pi (area / pi = aref^2). */
-static void e2_sums(const phi_view* v, const ora_ca_cfg* cfg, double* H, double* A) {
+ * and A = sum over the reference layer window of chi / pi (area / pi =
+ * aref^2). */
+static void e2_sums(const phi_view* v, const ora_ca_cfg* cfg, double rcut, double* H, double* A) {
   int kref = cfg->z_solid_top + cfg->offset;
   int kend = e2_column_end(v, cfg);
   double h = 0.5 * indicator(v, cfg->eps, cfg->ic, cfg->jc, kref);
   for (int k = kref + 1; k < kend; ++k) h += indicator(v, cfg->eps, cfg->ic, cfg->jc, k);
   double s = 0.0;
   for (int y = 0; y < v->L->ny; ++y)
-    for (int x = 0; x < v->L->nx; ++x) s += indicator(v, cfg->eps, x, y, kref);
+    for (int x = 0; x < v->L->nx; ++x)
+      if (in_window(v, cfg, rcut, x, y)) s += indicator(v, cfg->eps, x, y, kref);
   *H = h;
   *A = s / M_PI;
 }
@@ -529,7 +564,8 @@ int ora_contact_angle_phi(const ora_lattice* L, const ora_ca_cfg* cfg, const dou
 
   /* E2: smoothed indicator sums */
   double H, A;
-  e2_sums(&v, cfg, &H, &A);
+  double rcut = e2_window(&v, cfg, &flags);
+  e2_sums(&v, cfg, rcut, &H, &A);
   out->H_e2 = H;
   out->aref_e2 = sqrt(A);
   if (!(H > 0.0)) {
@@ -570,7 +606,9 @@ int ora_ca_seed(const ora_lattice* L, const ora_ca_cfg* cfg, double dL_dtheta, d
   int kref = cfg->z_solid_top + cfg->offset;
   double d = kref - (cfg->z_solid_top + 0.5);
   double H, A;
-  e2_sums(&v, cfg, &H, &A);
+  int wflags = 0;
+  double rcut = e2_window(&v, cfg, &wflags);
+  e2_sums(&v, cfg, rcut, &H, &A);
   int rc = 0;
   if (H > 0.0) {
     double h = H + d;
@@ -586,7 +624,8 @@ int ora_ca_seed(const ora_lattice* L, const ora_ca_cfg* cfg, double dL_dtheta, d
       double* g = (double*)calloc(L->N, sizeof(double)); /* dtheta/dphi */
       for (int y = 0; y < L->ny; ++y)
         for (int x = 0; x < L->nx; ++x)
-          g[node_at(L, x, y, kref)] += dth_dA * dindicator(&v, cfg->eps, x, y, kref) / M_PI;
+          if (in_window(&v, cfg, rcut, x, y))
+            g[node_at(L, x, y, kref)] += dth_dA * dindicator(&v, cfg->eps, x, y, kref) / M_PI;
       g[node_at(L, cfg->ic, cfg->jc, kref)] +=
           0.5 * dth_dH * dindicator(&v, cfg->eps, cfg->ic, cfg->jc, kref);
       int kend = e2_column_end(&v, cfg);

@@ -74,6 +74,7 @@ typedef struct {
 #define ORA_CA_NO_APEX   16   /* no phi crossing above the reference layer */
 #define ORA_CA_NO_DROP   32   /* no droplet on the column: angle is NaN */
 #define ORA_CA_E2_EMPTY  64   /* E2 column height H <= 0 */
+#define ORA_CA_E2_WHOLE_LAYER 128 /* E2 summed the whole reference layer */
 
 typedef struct ora_lattice ora_lattice;
 

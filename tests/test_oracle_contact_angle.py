@@ -102,3 +102,33 @@ def test_e2_seed_matches_central_differences(ora):
         ad = float(np.sum(lam * v))
         assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-3)
     L.set_state(s0)
+
+
+@pytest.mark.parametrize("theta", [90.0, 120.0])
+def test_second_droplet_in_reference_layer_is_ignored(box, theta):
+    """A second, small droplet on the wall away from the column (centred on
+    the box corner, so it wraps over all four corners) adds A-rich nodes to
+    the reference layer; E2 sums only the disk around the column, so neither
+    estimator moves."""
+    L, shape = box
+    cfg = W.ca_cfg(shape[2], shape[1])
+    phi = cap_phi(shape, 24.0, theta, 0.5, (cfg["ic"], cfg["jc"]))
+    other = np.maximum(phi, cap_phi(shape, 7.0, 90.0, 0.5, (0.0, 0.0)))
+    for dx in (shape[2], 0):
+        for dy in (shape[1], 0):
+            other = np.maximum(other, cap_phi(shape, 7.0, 90.0, 0.5, (float(dx), float(dy))))
+    a = L.contact_angle_phi(cfg, phi)
+    b = L.contact_angle_phi(cfg, other)
+    kref = cfg["z_solid_top"] + cfg["offset"]
+    assert (other[kref] > 0).sum() > (phi[kref] > 0).sum() + 50
+    assert b["flags"] & ~O.CA_RAY_LIMIT == 0
+    assert abs(a["theta_e1"] - b["theta_e1"]) < 1e-12
+    assert abs(a["theta_e2"] - b["theta_e2"]) < 1e-12
+    assert abs(b["theta_e2"] - theta) < 0.5
+
+
+def test_whole_layer_when_reference_is_outside(box):
+    L, shape = box
+    cfg = W.ca_cfg(shape[2], shape[1], z_solid_top=0, offset=5)
+    out = L.contact_angle_phi(cfg, cap_phi(shape, 24.0, 25.0, 0.5, (cfg["ic"], cfg["jc"])))
+    assert out["flags"] & O.CA_NO_REF and out["flags"] & O.CA_E2_WHOLE_LAYER
