@@ -205,6 +205,27 @@ def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):
             "speedup": round(ts / tb, 3)}
 
 
+def copy_probe(torch, stream, nbytes=1 << 30, reps=20):
+    """Attainable HBM bandwidth: a plain device-to-device copy of nbytes
+    (read + write counted), timed with events on the same stream."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * n * 8, "us": round(ms * 1e3, 2),
+            "GBs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(W, seconds):
     import oracle
     c = W.config_throughput(delta=0.2)
@@ -234,7 +255,9 @@ def main():
     ap.add_argument("--theta-steps", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="main workload only")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every compiled variant first instead of the library defaults")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -253,7 +276,7 @@ def main():
     stream = torch.cuda.Stream()
 
     tile64 = tile32 = None  # library default variant and z-chunk
-    if not args.no_autotune:
+    if args.autotune:
         tile64, ms64 = autotuned_tile(scd, W, "f64", stream)
         tile32, ms32 = autotuned_tile(scd, W, "f32", stream)
         log(f"autotune: f64 {tile64} {ms64:.4f} ms/step, f32 {tile32} {ms32:.4f} ms/step")
@@ -284,8 +307,11 @@ def main():
                              "f32": adjoint_cost(scd, W, torch, stream, "f32")}
         log("batched vs sequential")
         result["batched"] = batched_vs_sequential(scd, W, torch, stream)
-    log("CPU oracle baseline")
-    result["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    result["copy_probe"] = copy_probe(torch, stream)
+    log("copy probe", result["copy_probe"])
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

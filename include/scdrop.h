@@ -117,6 +117,9 @@ typedef struct {
 #define SCD_CA_NO_DROP 32      /* phi <= 0 on the first fluid node of the
                                   column: angles are NaN, ENOINTERFACE */
 #define SCD_CA_E2_EMPTY 64     /* E2 column height <= 0 */
+#define SCD_CA_E2_WHOLE_LAYER 128 /* phi <= 0 on the column at the reference
+                                     layer: E2 summed the whole layer instead
+                                     of the disk around the column */
 
 typedef struct scd_lattice scd_lattice;
 
@@ -182,18 +185,31 @@ scd_status scd_adjoint_reset(scd_lattice* h);
 scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
 
 /* Checkpointed gradient of L = (theta_E2 - target_deg)^2 (deg^2) after
- * nsteps steps from the densities d_rho_a, d_rho_b.  Forward: runs nsteps,
- * storing the state every ckpt_every steps into d_ckpt (ceil(nsteps /
- * ckpt_every) population buffers).  Backward: for each segment in reverse,
- * recomputes its states into d_seg (ckpt_every buffers) and applies the
- * adjoint steps; d_lam holds 2 population buffers of scratch.
- * h_out[0] = loss, h_out[1] = theta_E2 (deg); h_grad[5] = dL/dparams. */
+ * nsteps steps.  Forward: initialises from d_rho_a, d_rho_b (or, when both
+ * are NULL, starts from the current state), runs nsteps storing the state
+ * every ckpt_every steps into d_ckpt (ceil(nsteps / ckpt_every) population
+ * buffers), then measures theta_E2: h_out[0] = loss, h_out[1] = theta_E2
+ * (deg).  The parameters are constants of the run; the gradient is taken
+ * over these nsteps steps only.
+ * Backward (one level): for each segment in reverse, recomputes its states
+ * into d_seg (ckpt_every buffers) and applies the adjoint steps; d_lam holds
+ * 2 population buffers of scratch.  h_grad[5] = dL/d{rho_wall_A, rho_wall_B,
+ * g_ab, g_wall_A, g_wall_B}.  Needs the state left by the forward call; on
+ * return the state is the start of the first segment recomputed last.
+ * Backward (two levels): inside each level-1 segment, recomputes level-2
+ * checkpoints every K2 steps into d_mid (ceil(K1 / K2) buffers) and runs the
+ * one-level sweep on each sub-segment with d_seg of K2 buffers: each step is
+ * recomputed twice and the memory is ceil(n/K1) + ceil(K1/K2) + K2 + 2
+ * states instead of ceil(n/K) + K + 2. */
 scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
                             int64_t nsteps, int64_t ckpt_every, void* d_ckpt,
                             const scd_ca_cfg* cfg, double target_deg, double* h_out);
 scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t ckpt_every,
                              const void* d_ckpt, void* d_seg, void* d_lam,
                              const scd_ca_cfg* cfg, double target_deg, double* h_grad);
+scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_t K2,
+                              const void* d_ckpt, void* d_mid, void* d_seg, void* d_lam,
+                              const scd_ca_cfg* cfg, double target_deg, double* h_grad);
 
 /* ---- launch control (extension) ---- */
 /* The fused step is compiled in several variants: a tile of tx * ty

@@ -19,7 +19,7 @@ SCD_OK, SCD_EINVAL, SCD_EDEVICE, SCD_ENONFINITE, SCD_ENOINTERFACE, SCD_EUNSUPPOR
 SCD_F64, SCD_F32 = 0, 1
 SCD_WITH_ADJOINT = 1
 CA_FLAGS = {"NO_REF": 1, "E1_FLAT": 2, "E2_FLAT": 4, "RAY_LIMIT": 8, "NO_APEX": 16,
-            "NO_DROP": 32, "E2_EMPTY": 64}
+            "NO_DROP": 32, "E2_EMPTY": 64, "E2_WHOLE_LAYER": 128}
 
 
 class ScdParams(ctypes.Structure):
@@ -80,6 +80,8 @@ _PROTOS = {
     "scd_adjoint_read": [_VP, ctypes.POINTER(_D)],
     "scd_ckpt_forward": [_VP, _VP, _VP, _I64, _I64, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
     "scd_ckpt_backward": [_VP, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
+    "scd_ckpt_backward2": [_VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D,
+                           ctypes.POINTER(_D)],
     "scd_tile_set": [_VP, _I32, _I32],
     "scd_tile_get": [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
     "scd_tile_list": [ctypes.POINTER(_I32), _I32, ctypes.POINTER(_I32)],

@@ -132,6 +132,7 @@ struct scd_lattice {
   int64_t graph_steps;
   int graph_cur;
   bool batch_view;  // buffers belong to a batch
+  int64_t ckpt_base;  // step at which the last checkpointed forward began
   uint32_t* links() const { return (uint32_t*)(work + wl.links); }
   double* wd(size_t off) const { return (double*)(work + off); }
   void* wv(size_t off) const { return (void*)(work + off); }
@@ -139,14 +140,17 @@ struct scd_lattice {
 
 namespace {
 
-int default_variant() {
-  int v = variant_find(64, 4, 0, 1);
+// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet): FP64
+// runs best as the species-split z-march with streaming stores, FP32 with
+// both population sets in registers and shorter z-chunks.
+int default_variant(int dtype) {
+  int v = dtype == SCD_F64 ? variant_find(32, 8, 3, 2) : variant_find(32, 8, 0, 1);
   return v < 0 ? 0 : v;
 }
 
 void default_tile(scd_lattice* h) {
-  h->variant = default_variant();
-  h->zc = std::min(16, h->p.nz);
+  h->variant = default_variant(h->p.dtype);
+  h->zc = std::min(h->p.dtype == SCD_F64 ? 16 : 8, h->p.nz);
   h->remap = 1;
 }
 
@@ -239,6 +243,7 @@ scd_status scd_create(const scd_params* p, const uint8_t* d_solid, void* d_pop0,
   h->graph_steps = 0;
   h->graph_cur = 0;
   h->batch_view = false;
+  h->ckpt_base = 0;
   default_tile(h);
   hipError_t e = launch_links(d_solid, h->links(), p->nx, p->ny, p->nz, h->stream);
   if (e != hipSuccess) {
@@ -420,10 +425,15 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
                             double target_deg, double* h_out) {
   if (!h || !d_ckpt || !h_out) return fail(SCD_EINVAL, "NULL argument");
   if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if ((d_rho_a == nullptr) != (d_rho_b == nullptr))
+    return fail(SCD_EINVAL, "give both densities or neither");
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
-  st = scd_init_equilibrium(h, d_rho_a, d_rho_b);
-  if (st) return st;
+  if (d_rho_a) {
+    st = scd_init_equilibrium(h, d_rho_a, d_rho_b);
+    if (st) return st;
+  }
+  h->ckpt_base = h->step;
   const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
   for (int64_t t = 0; t < nsteps; t += K) {
     HIPCHK(hipMemcpyAsync((char*)d_ckpt + (size_t)(t / K) * bytes, h->pop[h->cur], bytes,
@@ -439,15 +449,39 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
   return SCD_OK;
 }
 
-scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
-                             void* d_seg, void* d_lam, const scd_ca_cfg* cfg, double target_deg,
-                             double* h_grad) {
-  if (!h || !d_ckpt || !d_seg || !d_lam || !h_grad) return fail(SCD_EINVAL, "NULL argument");
+// Reverse sweep over steps [t0, t1) (relative to the checkpointed forward)
+// whose starting state is in d_start: recompute the states into d_seg and
+// run the adjoint steps backwards, lambda ping-ponging in lam[2].
+static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
+                                  void* d_seg, void* lam[2], int* lc) {
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_start, bytes, hipMemcpyDeviceToDevice, h->stream));
+  h->step = h->ckpt_base + t0;
+  for (int64_t t = t0; t < t1; ++t) {
+    HIPCHK(hipMemcpyAsync((char*)d_seg + (size_t)(t - t0) * bytes, h->pop[h->cur], bytes,
+                          hipMemcpyDeviceToDevice, h->stream));
+    scd_status st = enqueue_steps(h, 1);
+    if (st) return st;
+  }
+  for (int64_t t = t1 - 1; t >= t0; --t) {
+    scd_status st = adjoint_enqueue(h, (const char*)d_seg + (size_t)(t - t0) * bytes, lam[*lc],
+                                    lam[1 - *lc], true);
+    if (st) return st;
+    *lc = 1 - *lc;
+  }
+  return SCD_OK;
+}
+
+static scd_status backward_start(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
+                                 void* d_lam, const scd_ca_cfg* cfg, double target_deg,
+                                 void* lam[2]) {
   if (!(h->p.flags & SCD_WITH_ADJOINT))
     return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
-  if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and ckpt_every must be >= 1");
-  if (h->step != nsteps) return fail(SCD_EINVAL, "state is at step %lld, expected %lld",
-                                     (long long)h->step, (long long)nsteps);
+  if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and checkpoint spacing must be >= 1");
+  if (h->step != h->ckpt_base + nsteps)
+    return fail(SCD_EINVAL, "state is at step %lld, expected %lld", (long long)h->step,
+                (long long)(h->ckpt_base + nsteps));
+  if (!d_ckpt || !d_lam) return fail(SCD_EINVAL, "NULL argument");
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
   const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
@@ -455,29 +489,59 @@ scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const vo
   st = scd_contact_angle(h, cfg, &ca);
   if (st) return st;
   const double dL_dtheta = 2.0 * (ca.theta_e2 - target_deg) * kRad2Deg;  // per radian
-  void* lam[2] = {d_lam, (char*)d_lam + bytes};
+  lam[0] = d_lam;
+  lam[1] = (char*)d_lam + bytes;
+  st = scd_ca_seed(h, cfg, dL_dtheta, lam[0]);
+  if (st) return st;
+  return scd_adjoint_reset(h);
+}
+
+scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
+                             void* d_seg, void* d_lam, const scd_ca_cfg* cfg, double target_deg,
+                             double* h_grad) {
+  if (!h || !d_seg || !h_grad) return fail(SCD_EINVAL, "NULL argument");
+  void* lam[2];
+  scd_status st = backward_start(h, nsteps, K, d_ckpt, d_lam, cfg, target_deg, lam);
+  if (st) return st;
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
   int lc = 0;
-  st = scd_ca_seed(h, cfg, dL_dtheta, lam[lc]);
-  if (st) return st;
-  st = scd_adjoint_reset(h);
-  if (st) return st;
   const int64_t nseg = (nsteps + K - 1) / K;
-  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
-    const int64_t t0 = sgi * K, t1 = std::min(nsteps, t0 + K);
-    HIPCHK(hipMemcpyAsync(h->pop[h->cur], (const char*)d_ckpt + (size_t)sgi * bytes, bytes,
+  for (int64_t s = nseg - 1; s >= 0; --s) {
+    st = reverse_segment(h, s * K, std::min(nsteps, s * K + K), (const char*)d_ckpt + (size_t)s * bytes,
+                         d_seg, lam, &lc);
+    if (st) return st;
+  }
+  return scd_adjoint_read(h, h_grad);
+}
+
+scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_t K2,
+                              const void* d_ckpt, void* d_mid, void* d_seg, void* d_lam,
+                              const scd_ca_cfg* cfg, double target_deg, double* h_grad) {
+  if (!h || !d_mid || !d_seg || !h_grad) return fail(SCD_EINVAL, "NULL argument");
+  if (K2 < 1 || K2 > K1) return fail(SCD_EINVAL, "need 1 <= K2 <= K1");
+  void* lam[2];
+  scd_status st = backward_start(h, nsteps, K1, d_ckpt, d_lam, cfg, target_deg, lam);
+  if (st) return st;
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  int lc = 0;
+  const int64_t nseg = (nsteps + K1 - 1) / K1;
+  for (int64_t s = nseg - 1; s >= 0; --s) {
+    const int64_t t0 = s * K1, t1 = std::min(nsteps, t0 + K1);
+    // level 2: checkpoints every K2 steps inside the segment
+    HIPCHK(hipMemcpyAsync(h->pop[h->cur], (const char*)d_ckpt + (size_t)s * bytes, bytes,
                           hipMemcpyDeviceToDevice, h->stream));
-    h->step = t0;
-    for (int64_t t = t0; t < t1; ++t) {
-      HIPCHK(hipMemcpyAsync((char*)d_seg + (size_t)(t - t0) * bytes, h->pop[h->cur], bytes,
+    h->step = h->ckpt_base + t0;
+    for (int64_t t = t0; t < t1; t += K2) {
+      HIPCHK(hipMemcpyAsync((char*)d_mid + (size_t)((t - t0) / K2) * bytes, h->pop[h->cur], bytes,
                             hipMemcpyDeviceToDevice, h->stream));
-      st = enqueue_steps(h, 1);
+      st = enqueue_steps(h, std::min(K2, t1 - t));
       if (st) return st;
     }
-    for (int64_t t = t1 - 1; t >= t0; --t) {
-      st = adjoint_enqueue(h, (const char*)d_seg + (size_t)(t - t0) * bytes, lam[lc], lam[1 - lc],
-                           true);
+    const int64_t nsub = (t1 - t0 + K2 - 1) / K2;
+    for (int64_t u = nsub - 1; u >= 0; --u) {
+      st = reverse_segment(h, t0 + u * K2, std::min(t1, t0 + u * K2 + K2),
+                           (const char*)d_mid + (size_t)u * bytes, d_seg, lam, &lc);
       if (st) return st;
-      lc = 1 - lc;
     }
   }
   return scd_adjoint_read(h, h_grad);
@@ -789,7 +853,7 @@ scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const
   b->desc_off[0] = L.desc[0];
   b->desc_off[1] = L.desc[1];
   b->items_off = L.items;
-  b->variant = default_variant();
+  b->variant = default_variant(p[0].dtype);
   b->zc = 16;
   b->stream = (hipStream_t)stream;
   b->parity = 0;

@@ -86,6 +86,12 @@ template <typename real>
 __device__ __forceinline__ void st_off(char* __restrict__ base, uint32_t boff, real v) {
   *reinterpret_cast<real*>(base + boff) = v;
 }
+// Streaming store: the new state is not read again within this step, so it
+// need not displace the state and halo lines the step still reads from L2.
+template <typename real>
+__device__ __forceinline__ void st_off_nt(char* __restrict__ base, uint32_t boff, real v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<real*>(base + boff));
+}
 
 // Streaming with mid-grid bounce-back (Sec. 2): the 38 post-stream
 // populations of fluid node i.  For each k the value comes from x - c_k, or

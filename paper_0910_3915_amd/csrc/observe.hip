@@ -186,8 +186,34 @@ __device__ double cap_theta(double aref2, double H, double h, double* R, double*
 enum {
   R_TH1 = 0, R_H1, R_A1, R_R1, R_AREF1, R_BH1,
   R_TH2, R_H2, R_A2, R_R2, R_AREF2, R_BH2,
-  R_CX, R_CY, R_FLAGS, R_STATUS, R_DTH_DH, R_DTH_DA, R_KEND
+  R_CX, R_CY, R_FLAGS, R_STATUS, R_DTH_DH, R_DTH_DA, R_KEND, R_RCUT
 };
+
+// Radius of the disk around the column over which E2 sums the reference
+// layer: the largest of the four half-chords plus 4 lattice units (the
+// indicator's transition band), so that A-rich regions of the layer that are
+// not this droplet (a wall film, a second droplet) are left out.  Infinite
+// (whole layer) when phi <= 0 on the column at the reference layer.
+__device__ double e2_window(const CaGeom& g, const double* ref) {
+  if (!(ref[g.c.jc * g.nx + g.c.ic] > 0.0)) return __builtin_inf();
+  int f = 0;
+  double r = layer_ray(g, ref, 1, 0, &f);
+  r = fmax(r, layer_ray(g, ref, -1, 0, &f));
+  r = fmax(r, layer_ray(g, ref, 0, 1, &f));
+  r = fmax(r, layer_ray(g, ref, 0, -1, &f));
+  return r + 4.0;
+}
+
+// periodic (minimum image) distance along one axis
+__device__ __forceinline__ int image_dist(int a, int b, int n) {
+  const int d = a > b ? a - b : b - a;
+  return d < n - d ? d : n - d;
+}
+
+__device__ __forceinline__ bool in_window(const CaGeom& g, double rcut, int x, int y) {
+  const double dx = image_dist(x, g.c.ic, g.nx), dy = image_dist(y, g.c.jc, g.ny);
+  return dx * dx + dy * dy <= rcut * rcut;
+}
 
 __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ links, int nx,
                                                    int ny, int nz, CaDev c,
@@ -200,12 +226,13 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
   const double* ref = phi;
   const double* low = phi + A;
   const double* col = phi + 2 * A;
-  // layer sums: sum chi, centroid of phi > 0
+  // layer sums: sum chi inside the E2 window, centroid of phi > 0
+  const double rcut = e2_window(g, ref);
   double v[4] = {0, 0, 0, 0};
   for (int t = threadIdx.x; t < A; t += blockDim.x) {
     const int x = t % nx, y = t / nx;
     if (g.solid(x, y, kref)) continue;
-    v[0] += smoothstep((ref[t] + c.eps) / (2.0 * c.eps));
+    if (in_window(g, rcut, x, y)) v[0] += smoothstep((ref[t] + c.eps) / (2.0 * c.eps));
     if (ref[t] > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
   }
   block_sum<4>(v, sh);
@@ -213,8 +240,9 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
 
   const double nan = __builtin_nan("");
   int flags = 0;
-  double out[R_KEND + 1];
-  for (int j = 0; j <= R_KEND; ++j) out[j] = 0.0;
+  double out[R_RCUT + 1];
+  for (int j = 0; j <= R_RCUT; ++j) out[j] = 0.0;
+  out[R_RCUT] = rcut;
   out[R_CX] = v[3] > 0.0 ? v[1] / v[3] : nan;
   out[R_CY] = v[3] > 0.0 ? v[2] / v[3] : nan;
   const double zw = c.zs + 0.5, d = kref - zw;
@@ -253,6 +281,7 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
       }
     }
     // E2
+    if (isinf(rcut)) flags |= 128;  // SCD_CA_E2_WHOLE_LAYER
     auto chi = [&](int k) {
       if (g.solid(c.ic, c.jc, k)) return 0.0;
       return smoothstep((col[k] + c.eps) / (2.0 * c.eps));
@@ -289,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
   }
   out[R_FLAGS] = flags;
   out[R_STATUS] = status;
-  for (int j = 0; j <= R_KEND; ++j) res[j] = out[j];
+  for (int j = 0; j <= R_RCUT; ++j) res[j] = out[j];
 }
 
 hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
@@ -319,6 +348,8 @@ __global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, in
   const int kref = c.zs + c.off;
   const int kend = (int)res[R_KEND];
   const double dH = res[R_DTH_DH], dA = res[R_DTH_DA];
+  const CaGeom g{nx, ny, nz, links, c};
+  const double rcut = res[R_RCUT];
   const int total = A + nz;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
     int x, y, z;
@@ -330,7 +361,7 @@ __global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, in
     const double dchi = dsmoothstep((p + c.eps) / (2.0 * c.eps)) / (2.0 * c.eps);
     double gr;
     if (t < A) {
-      gr = dA * dchi / M_PI;
+      gr = in_window(g, rcut, x, y) ? dA * dchi / M_PI : 0.0;
       if (x == c.ic && y == c.jc) gr += 0.5 * dH * dchi;
     } else {
       gr = dH * dchi;

@@ -188,11 +188,29 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   bool solid_cur = true, solid_next = true;
 
   // e of plane zr (raw, may lie outside [0, nz)) into ring slot zr & 3; the
-  // interior populations are kept in nout when keep is set.
+  // interior populations are kept in nout when keep is set.  The halo is
+  // pulled first, so that its loads are never in flight together with both
+  // population sets of the register variant.
   auto plane = [&](int zr, bool keep, real(&nout)[38], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
     E2<real>* slot = lds + (zr & 3) * T::P;
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      const uint32_t lb = L.links[i];
+      E2<real> e;
+      if (lb & SELF_SOLID) {
+        e = ewall;
+      } else {
+        real ra, rb;
+        pull_density(L.src, N, i, hx[h], hy[h], zs, nx, ny, lb, ra, rb);
+        e = fluid_e(L.ph, ra, rb);
+      }
+      slot[hpos[h]] = e;
+    }
+    phase_fence();
     {
       const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
       const uint32_t lb = L.links[i];
@@ -212,22 +230,6 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
         e = fluid_e(L.ph, ra, rb);
       }
       slot[pos] = e;
-    }
-    if (VAR == VAR_REPULL) phase_fence();
-#pragma unroll
-    for (int h = 0; h < T::HPT; ++h) {
-      if (!hval[h]) continue;
-      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
-      const uint32_t lb = L.links[i];
-      E2<real> e;
-      if (lb & SELF_SOLID) {
-        e = ewall;
-      } else {
-        real ra, rb;
-        pull_density(L.src, N, i, hx[h], hy[h], zs, nx, ny, lb, ra, rb);
-        e = fluid_e(L.ph, ra, rb);
-      }
-      slot[hpos[h]] = e;
     }
   };
 
@@ -274,6 +276,364 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Species-split z-march.  Each wave covers 32 nodes of a tile row: lanes
+// 0-31 carry species A, lanes 32-63 species B of the same nodes, so every
+// thread pulls, collides and stores the 19 populations of one species, and
+// one load instruction reads two contiguous 32-node segments.  The two
+// species of a node meet through a cross-half-wave swap (__shfl_xor by 32)
+// of their density and momentum.  A thread of species a writes e^{b} =
+// G^{b} psi^{a} of its node into the LDS ring (the value the *other*
+// species' force needs), so halo nodes need no exchange at all: a halo task
+// pulls one species' 19 populations of one node.
+template <typename real>
+__device__ __forceinline__ void pull19(const real* __restrict__ src, int N, int a, int i,
+                                       const int (&xs)[3], const int (&ys)[3], const int (&zs)[3],
+                                       int nx, int ny, uint32_t lb, real (&n)[19]) {
+  const char* __restrict__ base = reinterpret_cast<const char*>(src + (size_t)a * Q * N);
+  constexpr uint32_t S = sizeof(real);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int j = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const bool bb = (lb >> OPP[k]) & 1u;
+    const uint32_t off = bb ? ((uint32_t)OPP[k] * (uint32_t)N + (uint32_t)i) * S
+                            : ((uint32_t)k * (uint32_t)N + (uint32_t)j) * S;
+    n[k] = ld_off<real>(base, off);
+  }
+}
+
+// e value written by a thread of species a: what species b = 1 - a feels
+// from this node (Eq. SCforce at fluid nodes, the wall model at walls).
+template <typename real>
+__device__ __forceinline__ real e_from(const Phys<real>& ph, int a, bool wall, real rho_a) {
+  const int b = 1 - a;
+  return wall ? ph.gw[b] * ph.psiw[a] : ph.gab * psi_of(ph.psi_form, rho_a);
+}
+
+template <int TX, int TY>
+struct SplitTile {
+  static constexpr int NODES = TX * TY;
+  static constexpr int NT = 2 * NODES;  // threads
+  static constexpr int LX = TX + 2;
+  static constexpr int P = LX * (TY + 2);
+  static constexpr int R = 2 * LX + 2 * TY;           // halo nodes
+  static constexpr int TASKS = 2 * R;                  // halo (node, species) pulls
+  static constexpr int HPT = (TASKS + NT - 1) / NT;
+  static_assert(TX % 32 == 0, "a half-wave covers 32 nodes of one row");
+};
+
+template <typename real, int TX, int TY, bool NT_STORE>
+__device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, int by, int za,
+                                                int zb, real* __restrict__ lds) {
+  auto store = [](char* base, uint32_t off, real v) {
+    if constexpr (NT_STORE) st_off_nt<real>(base, off, v);
+    else st_off<real>(base, off, v);
+  };
+  using T = SplitTile<TX, TY>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int a = lane >> 5;                          // species of this thread
+  const int node = wave * 32 + (lane & 31);         // node of the tile
+  const int tx = node % TX, ty = node / TX;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int x0 = bx * TX, y0 = by * TY;
+  const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  int xs[3], ys[3];
+  axis3(wrap_index(x0 + tx, nx), nx, xs);
+  axis3(wrap_index(y0 + ty, ny), ny, ys);
+  const int pos = (ty + 1) * T::LX + (tx + 1);
+  // LDS ring: 4 planes x 2 species x P positions; plane slot s, species c
+  auto ring = [&](int zr, int c) { return lds + ((zr & 3) * 2 + c) * T::P; };
+
+  // halo tasks (node position, species) dealt lane-major over the waves
+  constexpr int HW = T::HPT * T::NT / 64;
+  int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
+  bool hval[T::HPT];
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) {
+    const int sl = tid + h * T::NT;
+    const int t = (sl & 63) * HW + (sl >> 6);
+    hval[h] = t < T::TASKS;
+    const int q = t >> 1;
+    hsp[h] = t & 1;
+    int lx, ly;
+    if (q < T::LX) { ly = -1; lx = q - 1; }
+    else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
+    else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
+    else { lx = TX; ly = q - 2 * T::LX - TY; }
+    if (!hval[h]) { lx = 0; ly = 0; }
+    axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
+    axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
+    hpos[h] = (ly + 1) * T::LX + (lx + 1);
+  }
+
+  real ncur[19], nnext[19];
+  bool solid_cur = true, solid_next = true;
+
+  auto plane = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
+    int zs[3];
+    axis3(wrap_index(zr, nz), nz, zs);
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      const uint32_t lb = L.links[i];
+      const bool wall = lb & SELF_SOLID;
+      real r = 0;
+      if (!wall) {
+        real m[19];
+        pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lb, m);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += m[k];
+      }
+      ring(zr, 1 - hsp[h])[hpos[h]] = e_from(L.ph, hsp[h], wall, r);
+    }
+    phase_fence();
+    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+    const uint32_t lb = L.links[i];
+    solid_out = (lb & SELF_SOLID) != 0;
+    real r = 0;
+    if (!solid_out) {
+      if (keep) {
+        pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, nout);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += nout[k];
+      } else {
+        real m[19];
+        pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, m);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += m[k];
+      }
+    }
+    ring(zr, 1 - a)[pos] = e_from(L.ph, a, solid_out, r);
+  };
+
+  const Phys<real>& ph = L.ph;
+  plane(za - 1, false, nnext, solid_next);
+  plane(za, true, ncur, solid_cur);
+  for (int p = za + 1; p <= zb; ++p) {
+    plane(p, p < zb, nnext, solid_next);
+    __syncthreads();
+    const int zc = p - 1;
+    // every lane takes part in the swap; inactive and wall lanes carry zeros
+    real rho, jx, jy, jz;
+    moments(ncur, rho, jx, jy, jz);
+    const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
+    const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
+    if (active && !solid_cur) {
+      // Eq. (SCforce) on species a: S^a = sum_k W_k e^a(x + c_k) c_k
+      const real* sm = ring(zc - 1, a);
+      const real* s0 = ring(zc, a);
+      const real* sp = ring(zc + 1, a);
+      real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        const real* s = CZ[k] < 0 ? sm : (CZ[k] > 0 ? sp : s0);
+        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const real e = w * s[pos + CY[k] * T::LX + CX[k]];
+        if (CX[k]) sx += CX[k] * e;
+        if (CY[k]) sy += CY[k] * e;
+        if (CZ[k]) sz += CZ[k] * e;
+      }
+      const real psi_a = psi_of(ph.psi_form, rho);
+      // the common velocity, with the two species in a fixed order so that
+      // both halves of the wave compute the same value
+      const real rA = a ? rho_o : rho, rB = a ? rho : rho_o;
+      const real jAx = a ? jx_o : jx, jBx = a ? jx : jx_o;
+      const real jAy = a ? jy_o : jy, jBy = a ? jy : jy_o;
+      const real jAz = a ? jz_o : jz, jBz = a ? jz : jz_o;
+      const real itA = ph.inv_tau[0], itB = ph.inv_tau[1];
+      const real iR = real(1) / (rA * itA + rB * itB);
+      const real sh = ph.tau[a] / rho;
+      const real ux = (jAx * itA + jBx * itB) * iR + sh * (-psi_a * sx);
+      const real uy = (jAy * itA + jBy * itB) * iR + sh * (-psi_a * sy);
+      const real uz = (jAz * itA + jBz * itB) * iR + sh * (-psi_a * sz);
+      const real uu = ux * ux + uy * uy + uz * uz;
+      const real it = ph.inv_tau[a];
+      const int i = (zc * ny + ys[1]) * nx + xs[1];
+      char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+      constexpr uint32_t S = sizeof(real);
+      real moving = 0;
+#pragma unroll
+      for (int k = 1; k < Q; k += 2) {
+        const int o = k + 1;
+        const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+        real fk, fo;
+        equilibrium_pair(real(WEIGHT[k]) * rho, s, uu, fk, fo);
+        moving += fk + fo;
+        store(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, ncur[k] + (fk - ncur[k]) * it);
+        store(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, ncur[o] + (fo - ncur[o]) * it);
+      }
+      const real eq0 = rho - moving;
+      store(out, (uint32_t)i * S, ncur[0] + (eq0 - ncur[0]) * it);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ncur[k] = nnext[k];
+    solid_cur = solid_next;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined species-split z-march.  Iteration p issues the loads of
+// plane p (interior and halo), collides plane p - 2 while they are in
+// flight, then turns plane p into e values.  Collision of plane c needs e
+// on planes c - 1, c, c + 1, all written before the barrier that ended
+// iteration c + 1; iteration p writes ring slot p & 3 while the collision
+// reads slots (p - 3, p - 2, p - 1) & 3, so one barrier per plane suffices.
+// Three population sets are live per thread (planes p - 2, p - 1, p).
+template <typename real, int TX, int TY>
+__device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, int by, int za,
+                                               int zb, real* __restrict__ lds) {
+  using T = SplitTile<TX, TY>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int a = lane >> 5;
+  const int node = wave * 32 + (lane & 31);
+  const int tx = node % TX, ty = node / TX;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int x0 = bx * TX, y0 = by * TY;
+  const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  int xs[3], ys[3];
+  axis3(wrap_index(x0 + tx, nx), nx, xs);
+  axis3(wrap_index(y0 + ty, ny), ny, ys);
+  const int pos = (ty + 1) * T::LX + (tx + 1);
+  auto ring = [&](int zr, int c) { return lds + ((zr & 3) * 2 + c) * T::P; };
+
+  constexpr int HW = T::HPT * T::NT / 64;
+  int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
+  bool hval[T::HPT];
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) {
+    const int sl = tid + h * T::NT;
+    const int t = (sl & 63) * HW + (sl >> 6);
+    hval[h] = t < T::TASKS;
+    const int q = t >> 1;
+    hsp[h] = t & 1;
+    int lx, ly;
+    if (q < T::LX) { ly = -1; lx = q - 1; }
+    else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
+    else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
+    else { lx = TX; ly = q - 2 * T::LX - TY; }
+    if (!hval[h]) { lx = 0; ly = 0; }
+    axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
+    axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
+    hpos[h] = (ly + 1) * T::LX + (lx + 1);
+  }
+  const Phys<real>& ph = L.ph;
+
+  real n0[19], n1[19], n2[19];       // planes p - 2, p - 1, p
+  real hm[T::HPT][19];               // halo pulls of plane p
+  bool s0 = true, s1 = true, s2 = true;
+  bool hw[T::HPT];
+
+  // issue the loads of plane zr (halo and interior)
+  auto load_plane = [&](int zr, real(&nout)[19], bool& solid_out) {
+    int zs[3];
+    axis3(wrap_index(zr, nz), nz, zs);
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      hw[h] = true;
+      if (!hval[h]) continue;
+      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      const uint32_t lb = L.links[i];
+      hw[h] = lb & SELF_SOLID;
+      if (!hw[h]) pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lb, hm[h]);
+    }
+    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+    const uint32_t lb = L.links[i];
+    solid_out = (lb & SELF_SOLID) != 0;
+    if (!solid_out) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, nout);
+  };
+  // e values of plane zr from the loaded populations
+  auto finish_plane = [&](int zr, const real(&nin)[19], bool solid_in) {
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      real r = 0;
+      if (!hw[h]) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += hm[h][k];
+      }
+      ring(zr, 1 - hsp[h])[hpos[h]] = e_from(ph, hsp[h], hw[h], r);
+    }
+    real r = 0;
+    if (!solid_in) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) r += nin[k];
+    }
+    ring(zr, 1 - a)[pos] = e_from(ph, a, solid_in, r);
+  };
+  auto collide = [&](int zc, const real(&n)[19], bool solid) {
+    real rho, jx, jy, jz;
+    moments(n, rho, jx, jy, jz);
+    const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
+    const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
+    if (!active || solid) return;
+    const real* sm = ring(zc - 1, a);
+    const real* sc = ring(zc, a);
+    const real* sp = ring(zc + 1, a);
+    real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const real* s = CZ[k] < 0 ? sm : (CZ[k] > 0 ? sp : sc);
+      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+      const real e = w * s[pos + CY[k] * T::LX + CX[k]];
+      if (CX[k]) sx += CX[k] * e;
+      if (CY[k]) sy += CY[k] * e;
+      if (CZ[k]) sz += CZ[k] * e;
+    }
+    const real psi_a = psi_of(ph.psi_form, rho);
+    const real rA = a ? rho_o : rho, rB = a ? rho : rho_o;
+    const real jAx = a ? jx_o : jx, jBx = a ? jx : jx_o;
+    const real jAy = a ? jy_o : jy, jBy = a ? jy : jy_o;
+    const real jAz = a ? jz_o : jz, jBz = a ? jz : jz_o;
+    const real itA = ph.inv_tau[0], itB = ph.inv_tau[1];
+    const real iR = real(1) / (rA * itA + rB * itB);
+    const real shf = ph.tau[a] / rho;
+    const real ux = (jAx * itA + jBx * itB) * iR + shf * (-psi_a * sx);
+    const real uy = (jAy * itA + jBy * itB) * iR + shf * (-psi_a * sy);
+    const real uz = (jAz * itA + jBz * itB) * iR + shf * (-psi_a * sz);
+    const real uu = ux * ux + uy * uy + uz * uz;
+    const real it = ph.inv_tau[a];
+    const int i = (zc * ny + ys[1]) * nx + xs[1];
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+    constexpr uint32_t S = sizeof(real);
+    real moving = 0;
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const int o = k + 1;
+      const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+      real fk, fo;
+      equilibrium_pair(real(WEIGHT[k]) * rho, s, uu, fk, fo);
+      moving += fk + fo;
+      st_off_nt<real>(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, n[k] + (fk - n[k]) * it);
+      st_off_nt<real>(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, n[o] + (fo - n[o]) * it);
+    }
+    const real eq0 = rho - moving;
+    st_off_nt<real>(out, (uint32_t)i * S, n[0] + (eq0 - n[0]) * it);
+  };
+
+  // prologue: planes za - 1 and za
+  load_plane(za - 1, n1, s1);
+  finish_plane(za - 1, n1, s1);
+  load_plane(za, n1, s1);
+  finish_plane(za, n1, s1);
+  __syncthreads();
+  for (int p = za + 1; p <= zb + 1; ++p) {
+    const bool have = p <= zb;  // plane p is still needed for its e values
+    if (have) load_plane(p, n2, s2);
+    phase_fence();
+    if (p - 2 >= za) collide(p - 2, n0, s0);
+    phase_fence();
+    if (have) finish_plane(p, n2, s2);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < Q; ++k) { n0[k] = n1[k]; n1[k] = n2[k]; }
+    s0 = s1;
+    s1 = s2;
+  }
+}
+
 // Map the hardware block id to a tile.  Workgroups are handed to the 8 XCDs
 // round-robin; with remap each XCD receives one contiguous range of tiles
 // (x fastest, then y, then z-chunk), so neighbouring tiles that share halo
@@ -291,28 +651,54 @@ __device__ __forceinline__ bool tile_of_block(int b, int total, int remap, int g
   return true;
 }
 
+constexpr int VAR_SPLIT = 2;     // species-split z-march
+constexpr int VAR_SPLIT_NT = 3;  // the same with streaming stores
+constexpr int VAR_PIPE = 4;      // software-pipelined species split, streaming stores
+
+template <typename real, int TX, int TY, int VAR>
+struct StepShape {
+  static constexpr bool SPLIT = VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE;
+  static constexpr int THREADS = SPLIT ? 2 * TX * TY : TX * TY;
+  static constexpr int LDS_REALS = SPLIT ? 8 * SplitTile<TX, TY>::P : 8 * Tile<TX, TY>::P;
+};
+
+template <typename real, int TX, int TY, int VAR>
+__device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, int za, int zb,
+                                         real* lds) {
+  if constexpr (VAR == VAR_SPLIT)
+    step_tile_split<real, TX, TY, false>(L, bx, by, za, zb, lds);
+  else if constexpr (VAR == VAR_SPLIT_NT)
+    step_tile_split<real, TX, TY, true>(L, bx, by, za, zb, lds);
+  else if constexpr (VAR == VAR_PIPE)
+    step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
+  else
+    step_tile<real, TX, TY, VAR>(L, bx, by, za, zb, reinterpret_cast<E2<real>*>(lds));
+}
+
 template <typename real, int TX, int TY, int VAR, int WPE>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+__global__ __launch_bounds__((StepShape<real, TX, TY, VAR>::THREADS))
+__attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_step(LatDev<real> L, int gx, int gy, int nchunks, int zc, int remap) {
-  __shared__ E2<real> lds[4 * Tile<TX, TY>::P];
+  __shared__ __align__(16) real lds[StepShape<real, TX, TY, VAR>::LDS_REALS];
   int bx, by, bz;
   if (!tile_of_block(blockIdx.x, gx * gy * nchunks, remap, gx, gy, bx, by, bz)) return;
   const int za = bz * zc;
   const int zb = min(za + zc, L.nz);
-  step_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds);
+  run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds);
 }
 
 // Batched: a persistent grid walks a list of (lattice, tile) items.
 template <typename real, int TX, int TY, int VAR, int WPE>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+__global__ __launch_bounds__((StepShape<real, TX, TY, VAR>::THREADS))
+__attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_step_batch(const LatDev<real>* __restrict__ lats, const int4* __restrict__ items,
                   int nitems) {
-  __shared__ E2<real> lds[4 * Tile<TX, TY>::P];
+  __shared__ __align__(16) real lds[StepShape<real, TX, TY, VAR>::LDS_REALS];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];  // lattice, bx, by, (z-chunk << 16) | first plane
     const LatDev<real> L = lats[w.x];
     const int zc = w.w >> 16, za = w.w & 0xffff;
-    step_tile<real, TX, TY, VAR>(L, w.y, w.z, za, min(za + zc, L.nz), lds);
+    run_tile<real, TX, TY, VAR>(L, w.y, w.z, za, min(za + zc, L.nz), lds);
     __syncthreads();  // the next item rewrites the LDS ring
   }
 }
@@ -454,8 +840,9 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
 // Compiled variants (tx, ty, var, wpe): tile shape, z-march variant and
 // the minimum waves per SIMD the register allocation must allow.
 #define SCD_VARIANTS(X)                                                                   \
-  X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 0, 2) X(32, 8, 0, 2) X(32, 4, 0, 2) X(64, 2, 0, 2) \
-  X(64, 4, 0, 3) X(64, 4, 1, 1) X(32, 8, 1, 1) X(64, 8, 1, 2) X(16, 16, 1, 2) X(64, 4, 1, 4)
+  X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
+  X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 4, 2) X(64, 4, 4, 2) X(32, 8, 4, 2) \
+  X(64, 2, 4, 2) X(32, 4, 4, 3)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},
@@ -490,8 +877,8 @@ static hipError_t launch_step_t(const LatDev<real>& L, int variant, int zc, int 
   const int blocks = remap ? ((total + 7) / 8) * 8 : total;
 #define SCD_LAUNCH(a, b, v, w)                                                              \
   if (tx == a && ty == b && var == v && wpe == w) {                                         \
-    hipLaunchKernelGGL((k_step<real, a, b, v, w>), dim3(blocks), dim3(a * b), 0, s, L, gx, gy, \
-                       nch, zc, remap);                                                     \
+    hipLaunchKernelGGL((k_step<real, a, b, v, w>), dim3(blocks),                            \
+                       dim3(StepShape<real, a, b, v>::THREADS), 0, s, L, gx, gy, nch, zc, remap); \
     return hipGetLastError();                                                               \
   }
   SCD_VARIANTS(SCD_LAUNCH)
@@ -520,7 +907,8 @@ static hipError_t launch_batch_t(const void* lats, const void* items, int nitems
   const int var = kVariants[variant][2], wpe = kVariants[variant][3];
 #define SCD_LAUNCHB(a, b, v, w)                                                                 \
   if (tx == a && ty == b && var == v && wpe == w) {                                             \
-    hipLaunchKernelGGL((k_step_batch<real, a, b, v, w>), dim3(grid), dim3(a * b), 0, s,         \
+    hipLaunchKernelGGL((k_step_batch<real, a, b, v, w>), dim3(grid),                            \
+                       dim3(StepShape<real, a, b, v>::THREADS), 0, s,                           \
                        (const LatDev<real>*)lats, (const int4*)items, nitems);                  \
     return hipGetLastError();                                                                   \
   }

@@ -1,0 +1,165 @@
+"""Workload drivers on top of the library: the wall-asymmetry sweep, the
+gradient fit of the wall parameters to a target angle, and the structured-
+surface (posts) run.  Each prints JSON lines and returns a dict.
+
+    python -m paper_0910_3915_amd.experiments sweep --dtype f64
+    python -m paper_0910_3915_amd.experiments fit --dtype f64
+    python -m paper_0910_3915_amd.experiments posts --steps 100000
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .grad import ContactAngleFn, GradSetup
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+import workloads as W  # noqa: E402
+
+
+def emit(d):
+    print(json.dumps(d), flush=True)
+    return d
+
+
+def fluid_nodes(solid):
+    return int(np.count_nonzero(np.asarray(solid) == 0))
+
+
+def timed_steps(L, steps, stream, chunk=1000):
+    """Advance L by steps with captured graphs; returns seconds."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    g = min(chunk, steps) // 2 * 2
+    if g >= 2:
+        L.graph_capture(g)
+        while steps - done >= g:
+            L.graph_replay(1)
+            done += g
+    L.step(steps - done)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def sweep(dtype="f64", steps=20000, box="full", deltas=W.THROUGHPUT_DELTAS):
+    """Contact angle against the wall asymmetry rho_wall_A - rho_wall_B."""
+    stream = torch.cuda.Stream()
+    out = []
+    for d in deltas:
+        c = (W.config_throughput(delta=float(d), dtype=dtype) if box == "full"
+             else dict(W.config_throughput_twin(delta=float(d)), params=dict(
+                 W.config_throughput_twin(delta=float(d))["params"], dtype=dtype)))
+        L = B.Lattice(c["params"], c["solid"], stream=stream)
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        sec = timed_steps(L, steps, stream)
+        ca = L.contact_angle(c["ca"])
+        obs = L.observables()
+        out.append(emit({"exp": "sweep", "box": box, "dtype": dtype, "delta": float(d), "steps": steps,
+                         "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
+                         "mlups": fluid_nodes(c["solid"]) * steps / sec / 1e6, "mass": list(obs["mass"])}))
+    return {"sweep": out}
+
+
+def fit(dtype="f64", iters=50, steps=2000, ckpt=100, target=120.0):
+    """Gradient descent on the wall contents (rho_wall_A, rho_wall_B) through
+    the hand-written adjoint: loss L = (theta_E2 - target)^2 (deg^2) after
+    steps steps of the 64 x 64 x 48 droplet (cap radius 14), g_ab = g_wall =
+    0.12 held fixed (their gradients are reported).  Step size: Polyak's
+    rule eta = L / |grad L|^2 (known optimum L* = 0), i.e. half a Newton step
+    on the residual theta - target."""
+    c = W.config_gradient(dtype=dtype)
+    setup = GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], steps, ckpt, c["ca"], target)
+    p = torch.tensor([0.5, 0.5], dtype=torch.float64)
+    g_ab = 0.12
+    hist = []
+    for it in range(iters):
+        x = p.clone().requires_grad_(True)
+        wall = torch.cat([x, torch.tensor([g_ab, g_ab, g_ab], dtype=torch.float64)])
+        wall.retain_grad()
+        loss = ContactAngleFn.apply(wall, setup)
+        loss.backward()
+        gx = x.grad.clone()
+        rec = {"exp": "fit", "dtype": dtype, "iter": it, "loss": loss.item(), "theta_e2": setup.theta,
+               "rho_wall_A": float(p[0]), "rho_wall_B": float(p[1]),
+               "grad_full": [float(v) for v in wall.grad]}
+        hist.append(emit(rec))
+        nrm2 = float(gx @ gx)
+        if loss.item() < 1e-12 or nrm2 == 0.0:
+            break
+        p = torch.clamp(p - (loss.item() / nrm2) * gx, min=0.0)
+    setup.apply_params([float(p[0]), float(p[1]), g_ab, g_ab, g_ab])
+    final_loss = setup.forward()
+    res = emit({"exp": "fit_final", "dtype": dtype, "theta_e2": setup.theta, "loss": final_loss,
+                "rho_wall": [float(v) for v in p], "g_ab": g_ab, "iters": len(hist),
+                "optimizer": "gradient descent, Polyak step L/|grad L|^2",
+                "abs_error_deg": abs(setup.theta - target)})
+    return {"history": hist, "final": res}
+
+
+def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000):
+    """Droplet on a square array of posts (width 6, pitch 12, height 12) in
+    a 384 x 384 x 192 box, wall asymmetry -0.3; then one adjoint pass over
+    the last adjoint_steps steps with two-level checkpointing."""
+    c = W.config_posts(dtype=dtype)
+    stream = torch.cuda.Stream()
+    L = B.Lattice(c["params"], c["solid"], adjoint=adjoint_steps > 0, stream=stream)
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    nf = fluid_nodes(c["solid"])
+    best, ms = L.autotune(6, None)
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    emit({"exp": "posts", "fluid_nodes": nf, "tile": list(best), "tune_ms": ms})
+    run = steps - adjoint_steps
+    done, total_sec = 0, 0.0
+    while done < run:
+        n = min(report_every, run - done)
+        total_sec += timed_steps(L, n, stream)
+        done += n
+        ca = L.contact_angle(c["ca"])
+        obs = L.observables(raise_nonfinite=False)
+        emit({"exp": "posts", "step": L.step_count, "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"],
+              "flags": ca["flags"], "mass": list(obs["mass"]), "finite": obs["finite"],
+              "mlups": nf * done / total_sec / 1e6})
+    out = {"mlups": nf * done / total_sec / 1e6, "steps": done}
+    if adjoint_steps > 0:
+        setup = GradSetup(c["params"], c["solid"], None, None, adjoint_steps, K1, c["ca"], 150.0,
+                          lattice=L, inner=K2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = setup.forward()
+        t1 = time.perf_counter()
+        g = setup.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out.update(emit({"exp": "posts_adjoint", "steps": adjoint_steps, "theta_e2": setup.theta, "loss": loss,
+                         "grad": g, "forward_s": t1 - t0, "backward_s": t2 - t1,
+                         "backward_over_forward": (t2 - t1) / (t1 - t0)}))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["sweep", "fit", "posts"])
+    ap.add_argument("--dtype", default=None, help="f64 or f32 (posts default f32, others f64)")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--box", default="full")
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
+    a = ap.parse_args()
+    if a.what == "sweep":
+        sweep(a.dtype or "f64", a.steps or 20000, a.box)
+    elif a.what == "fit":
+        fit(a.dtype or "f64", a.iters, a.steps or 2000)
+    else:
+        posts(a.steps or 100000, a.adjoint_steps, a.dtype or "f32")
+
+
+if __name__ == "__main__":
+    main()

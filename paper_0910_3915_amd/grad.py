@@ -14,26 +14,39 @@ from . import binding as B
 
 
 class GradSetup:
-    """Buffers and settings of one differentiable run (caller keeps it alive)."""
+    """Buffers and settings of one differentiable run (caller keeps it alive).
+
+    ckpt_every = K stores a state every K steps and recomputes each segment
+    (one level).  With inner = K2 < K the backward pass also checkpoints
+    every K2 steps inside a segment (two levels), for lattices whose states
+    are too large to hold K of them.  rho_a = rho_b = None starts every
+    forward pass from the lattice's current state instead of re-initialising.
+    """
 
     def __init__(self, params, solid, rho_a, rho_b, nsteps, ckpt_every, ca_cfg, target_deg,
-                 device="cuda", stream=None):
-        self.lat = B.Lattice(params, solid, device=device, adjoint=True, stream=stream)
+                 device="cuda", stream=None, inner=None, lattice=None):
+        self.lat = lattice or B.Lattice(params, solid, device=device, adjoint=True, stream=stream)
         self.params = dict(params)
         self.nsteps = int(nsteps)
         self.K = int(ckpt_every)
+        self.K2 = int(inner) if inner else None
         self.cfg = B.make_ca_cfg(ca_cfg)
         self.target = float(target_deg)
         dev = self.lat.device
-        self.rho_a = B._device_f64(rho_a, dev).reshape(-1)
-        self.rho_b = B._device_f64(rho_b, dev).reshape(-1)
+        self.rho_a = None if rho_a is None else B._device_f64(rho_a, dev).reshape(-1)
+        self.rho_b = None if rho_b is None else B._device_f64(rho_b, dev).reshape(-1)
         nseg = (self.nsteps + self.K - 1) // self.K
         shape = (2, 19) + self.lat.shape
         dt = self.lat.dtype
         self.ckpt = torch.empty((nseg,) + shape, dtype=dt, device=dev)
-        self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
+        if self.K2:
+            self.mid = torch.empty(((self.K + self.K2 - 1) // self.K2,) + shape, dtype=dt, device=dev)
+            self.seg = torch.empty((self.K2,) + shape, dtype=dt, device=dev)
+        else:
+            self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
         self.lam = torch.empty((2,) + shape, dtype=dt, device=dev)
         self.theta = float("nan")
+        self.start = None if rho_a is not None else self.lat.get_state()
 
     def apply_params(self, values):
         v = [float(x) for x in values]
@@ -44,15 +57,27 @@ class GradSetup:
     def forward(self):
         self.lat._after_torch()
         out = (ctypes.c_double * 2)()
-        B.check(B.lib().scd_ckpt_forward(self.lat.h, B._ptr(self.rho_a), B._ptr(self.rho_b), self.nsteps,
-                                         self.K, B._ptr(self.ckpt), ctypes.byref(self.cfg), self.target, out))
+        if self.rho_a is None:
+            # every pass starts from the same stored state
+            self.lat.set_state(self.start, self.lat.step_count)
+            ra = rb = None
+        else:
+            ra, rb = B._ptr(self.rho_a), B._ptr(self.rho_b)
+        B.check(B.lib().scd_ckpt_forward(self.lat.h, ra, rb, self.nsteps, self.K, B._ptr(self.ckpt),
+                                         ctypes.byref(self.cfg), self.target, out))
         self.theta = out[1]
         return out[0]
 
     def backward(self):
         g = (ctypes.c_double * 5)()
-        B.check(B.lib().scd_ckpt_backward(self.lat.h, self.nsteps, self.K, B._ptr(self.ckpt), B._ptr(self.seg),
-                                          B._ptr(self.lam), ctypes.byref(self.cfg), self.target, g))
+        if self.K2:
+            B.check(B.lib().scd_ckpt_backward2(self.lat.h, self.nsteps, self.K, self.K2, B._ptr(self.ckpt),
+                                               B._ptr(self.mid), B._ptr(self.seg), B._ptr(self.lam),
+                                               ctypes.byref(self.cfg), self.target, g))
+        else:
+            B.check(B.lib().scd_ckpt_backward(self.lat.h, self.nsteps, self.K, B._ptr(self.ckpt),
+                                              B._ptr(self.seg), B._ptr(self.lam), ctypes.byref(self.cfg),
+                                              self.target, g))
         return list(g)
 
 
