@@ -68,39 +68,68 @@ def sweep(dtype="f64", steps=20000, box="full", deltas=W.THROUGHPUT_DELTAS):
     return {"sweep": out}
 
 
-def fit(dtype="f64", iters=50, steps=2000, ckpt=100, target=120.0):
+def fit(dtype="f64", iters=50, steps=2000, ckpt=100, target=120.0, max_step=0.05):
     """Gradient descent on the wall contents (rho_wall_A, rho_wall_B) through
     the hand-written adjoint: loss L = (theta_E2 - target)^2 (deg^2) after
     steps steps of the 64 x 64 x 48 droplet (cap radius 14), g_ab = g_wall =
-    0.12 held fixed (their gradients are reported).  Step size: Polyak's
-    rule eta = L / |grad L|^2 (known optimum L* = 0), i.e. half a Newton step
-    on the residual theta - target."""
+    0.12 held fixed (their gradients are reported).
+
+    Step along -grad L with the Gauss-Newton length for the single residual
+    r = theta - target (dp = -2 L grad L / |grad L|^2, the step that zeroes
+    the linearised r), capped at max_step in parameter space; a trial point
+    that raises the loss or loses the droplet halves the step (at most five
+    times).  Trials are forward-only; the gradient is taken through
+    ContactAngleFn at accepted points."""
     c = W.config_gradient(dtype=dtype)
     setup = GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], steps, ckpt, c["ca"], target)
-    p = torch.tensor([0.5, 0.5], dtype=torch.float64)
     g_ab = 0.12
-    hist = []
-    for it in range(iters):
-        x = p.clone().requires_grad_(True)
-        wall = torch.cat([x, torch.tensor([g_ab, g_ab, g_ab], dtype=torch.float64)])
-        wall.retain_grad()
+
+    def wall_of(p):
+        return torch.cat([p, torch.tensor([g_ab, g_ab, g_ab], dtype=torch.float64)])
+
+    def value_and_grad(p):
+        wall = wall_of(p).requires_grad_(True)
         loss = ContactAngleFn.apply(wall, setup)
         loss.backward()
-        gx = x.grad.clone()
-        rec = {"exp": "fit", "dtype": dtype, "iter": it, "loss": loss.item(), "theta_e2": setup.theta,
-               "rho_wall_A": float(p[0]), "rho_wall_B": float(p[1]),
-               "grad_full": [float(v) for v in wall.grad]}
-        hist.append(emit(rec))
+        return loss.item(), setup.theta, wall.grad.clone()
+
+    def trial(p):
+        setup.apply_params(wall_of(p).tolist())
+        try:
+            return setup.forward()
+        except B.ScdError:
+            return float("inf")
+
+    p = torch.tensor([0.5, 0.5], dtype=torch.float64)
+    loss, theta, gfull = value_and_grad(p)
+    hist = []
+    for it in range(iters):
+        gx = gfull[:2]
+        hist.append(emit({"exp": "fit", "dtype": dtype, "iter": it, "loss": loss, "theta_e2": theta,
+                          "rho_wall_A": float(p[0]), "rho_wall_B": float(p[1]),
+                          "grad_full": [float(v) for v in gfull]}))
         nrm2 = float(gx @ gx)
-        if loss.item() < 1e-12 or nrm2 == 0.0:
+        if loss < 1e-8 or nrm2 == 0.0:
             break
-        p = torch.clamp(p - (loss.item() / nrm2) * gx, min=0.0)
-    setup.apply_params([float(p[0]), float(p[1]), g_ab, g_ab, g_ab])
-    final_loss = setup.forward()
-    res = emit({"exp": "fit_final", "dtype": dtype, "theta_e2": setup.theta, "loss": final_loss,
+        dp = -2.0 * loss / nrm2 * gx
+        n = float(dp.norm())
+        if n > max_step:
+            dp *= max_step / n
+        t, accepted = 1.0, False
+        for _ in range(6):
+            q = torch.clamp(p + t * dp, min=0.0)
+            if trial(q) < loss:
+                accepted = True
+                break
+            t *= 0.5
+        if not accepted:
+            break
+        p = q
+        loss, theta, gfull = value_and_grad(p)
+    res = emit({"exp": "fit_final", "dtype": dtype, "theta_e2": theta, "loss": loss,
                 "rho_wall": [float(v) for v in p], "g_ab": g_ab, "iters": len(hist),
-                "optimizer": "gradient descent, Polyak step L/|grad L|^2",
-                "abs_error_deg": abs(setup.theta - target)})
+                "optimizer": "gradient descent, Gauss-Newton step length capped at %g, backtracking" % max_step,
+                "abs_error_deg": abs(theta - target)})
     return {"history": hist, "final": res}
 
 
