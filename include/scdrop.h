@@ -253,11 +253,22 @@ scd_status scd_batch_lattice(scd_batch* b, int32_t i, scd_lattice** view);
 scd_status scd_batch_init_equilibrium(scd_batch* b, int32_t i, const double* d_rho_a,
                                       const double* d_rho_b);
 /* Step variant (see scd_tile_list), z-chunk and number of persistent
- * workgroups (grid). */
+ * workgroups (grid); grid 0 (the default) launches one workgroup per
+ * (lattice, tile) item.  Defaults: FP32 64x4 one-node-per-thread tiles,
+ * FP64 the single-lattice default variant; 32-plane chunks. */
 scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t grid);
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps);
+/* Time every compiled variant x z-chunk {8, 16, 32, 64} x grid {one
+ * workgroup per item, 4 per compute unit} for steps_per_trial steps (plus one
+ * warm-up) and keep the fastest; h_best = {variant, zc, grid}, h_ms = its
+ * time per step.  The members advance by every trial step (re-initialise
+ * afterwards for a clean start).  cache_path (or NULL): JSON-lines file; a
+ * line with the same key (member shapes, dtype, device, variant count) is
+ * used without timing, a new result is appended.  Drops a captured graph. */
+scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
+                              int32_t* h_best, double* h_ms);
 
 /* Fill each of the 38 * N entries of the current state with value
  * (for tests of the observables) */

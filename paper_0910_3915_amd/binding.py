@@ -97,6 +97,7 @@ _PROTOS = {
     "scd_batch_step": [_VP, _I64],
     "scd_batch_graph_capture": [_VP, _I64],
     "scd_batch_graph_replay": [_VP, _I64],
+    "scd_batch_autotune": [_VP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_D)],
 }
 
 
@@ -395,6 +396,14 @@ class Batch:
 
     def step(self, n=1):
         check(lib().scd_batch_step(self.h, int(n)))
+
+    def autotune(self, steps_per_trial=3, cache_path=None):
+        """Fastest (variant, zc, grid) and its ms per step; members advance."""
+        best = (_I32 * 3)()
+        ms = _D()
+        path = cache_path.encode() if cache_path else None
+        check(lib().scd_batch_autotune(self.h, int(steps_per_trial), path, best, ctypes.byref(ms)))
+        return tuple(best), ms.value
 
     def graph_capture(self, nsteps):
         check(lib().scd_batch_graph_capture(self.h, int(nsteps)))

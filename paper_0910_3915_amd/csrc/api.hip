@@ -590,6 +590,31 @@ static std::string tune_key(const scd_lattice* h) {
   return o.str();
 }
 
+// The last line of the JSON-lines cache whose key matches: "best": [a, b, c].
+static bool cache_lookup3(const char* path, const std::string& key, int* best, double* ms) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  const std::string k = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(k) == std::string::npos) continue;
+    int a, c, d;
+    double t;
+    const char* s = strstr(line.c_str(), "\"best\": [");
+    const char* m = strstr(line.c_str(), "\"ms\": ");
+    if (!s || !m) continue;
+    if (sscanf(s, "\"best\": [%d, %d, %d]", &a, &c, &d) == 3 && sscanf(m, "\"ms\": %lf", &t) == 1) {
+      best[0] = a;
+      best[1] = c;
+      best[2] = d;
+      *ms = t;
+      found = true;
+    }
+  }
+  return found;
+}
+
 static bool cache_lookup(const char* path, const std::string& key, int* best, double* ms) {
   if (!path) return false;
   std::ifstream f(path);
@@ -802,6 +827,16 @@ scd_status batch_upload(scd_batch* b) {
   return SCD_OK;
 }
 
+// Default batch tile: with many (lattice, tile) items the z-halo re-reads of
+// short chunks cost more than the lost parallelism of long ones, so the
+// batch marches 32 planes per item; one workgroup per item (grid 0).
+void batch_default_tile(int dtype, int* variant, int* zc, int* grid) {
+  *variant = dtype == SCD_F64 ? default_variant(dtype) : variant_find(64, 4, 0, 1);
+  if (*variant < 0) *variant = default_variant(dtype);
+  *zc = 32;
+  *grid = 0;
+}
+
 void batch_drop_graph(scd_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -812,8 +847,9 @@ void batch_drop_graph(scd_batch* b) {
 
 scd_status batch_enqueue(scd_batch* b, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
+    const int grid = (b->grid <= 0 || b->grid > b->nitems) ? b->nitems : b->grid;
     HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity], b->arena + b->items_off,
-                             b->nitems, b->grid, b->variant, b->stream));
+                             b->nitems, grid, b->variant, b->stream));
     b->parity ^= 1;
     for (scd_lattice* v : b->views) {
       v->cur = b->parity;
@@ -853,18 +889,13 @@ scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const
   b->desc_off[0] = L.desc[0];
   b->desc_off[1] = L.desc[1];
   b->items_off = L.items;
-  b->variant = default_variant(p[0].dtype);
-  b->zc = 16;
+  batch_default_tile(p[0].dtype, &b->variant, &b->zc, &b->grid);
   b->stream = (hipStream_t)stream;
   b->parity = 0;
   b->graph = nullptr;
   b->gexec = nullptr;
   b->graph_steps = 0;
   b->graph_parity = 0;
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = cus * 4;
   for (int i = 0; i < n; ++i) {
     scd_lattice* v = nullptr;
     st = scd_create(&p[i], d_solid[i], b->arena + L.pop0[i], b->arena + L.pop1[i],
@@ -913,7 +944,7 @@ scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t
   if (!b) return fail(SCD_EINVAL, "NULL handle");
   if (variant < 0 || variant >= variant_count())
     return fail(SCD_EINVAL, "variant %d is not compiled", variant);
-  if (zc < 1 || grid < 1) return fail(SCD_EINVAL, "z-chunk and grid must be >= 1");
+  if (zc < 1 || grid < 0) return fail(SCD_EINVAL, "z-chunk must be >= 1 and grid >= 0");
   b->variant = variant;
   b->zc = zc;
   b->grid = grid;
@@ -948,6 +979,73 @@ scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps) {
   HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
   b->graph_steps = nsteps;
   b->graph_parity = par0;
+  return SCD_OK;
+}
+
+scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
+                              int32_t* best, double* best_ms) {
+  if (!b || !best || !best_ms) return fail(SCD_EINVAL, "NULL argument");
+  if (steps_per_trial < 2) return fail(SCD_EINVAL, "steps_per_trial must be >= 2");
+  // key: member count, a hash of the member shapes, dtype, device, variant count
+  uint64_t hsh = 1469598103934665603ull;
+  for (scd_lattice* v : b->views)
+    for (int d : {v->p.nx, v->p.ny, v->p.nz}) hsh = (hsh ^ (uint64_t)d) * 1099511628211ull;
+  std::ostringstream ko;
+  ko << "batch" << b->n << ":" << std::hex << hsh << std::dec << ":" << (b->dtype == SCD_F64 ? "f64" : "f32")
+     << ":" << device_name() << ":v" << variant_count();
+  const std::string key = ko.str();
+  int cached[3];
+  double cms;
+  if (cache_lookup3(cache_path, key, cached, &cms) && cached[0] >= 0 && cached[0] < variant_count()) {
+    scd_status st = scd_batch_set_tile(b, cached[0], cached[1], cached[2]);
+    if (st) return st;
+    for (int j = 0; j < 3; ++j) best[j] = cached[j];
+    *best_ms = cms;
+    return SCD_OK;
+  }
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double bms = 1e30;
+  int bb[3] = {b->variant, b->zc, b->grid};
+  const int zcs[] = {8, 16, 32, 64};
+  const int grids[] = {0, 4 * cus};
+  for (int i = 0; i < variant_count(); ++i)
+    for (int zc : zcs)
+      for (int grid : grids) {
+        scd_status st = scd_batch_set_tile(b, i, zc, grid);
+        if (st) return st;
+        st = batch_enqueue(b, 1);  // warm-up
+        if (st) return st;
+        HIPCHK(hipEventRecord(e0, b->stream));
+        st = batch_enqueue(b, steps_per_trial);
+        if (st) return st;
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / steps_per_trial;
+        if (per < bms) {
+          bms = per;
+          bb[0] = i;
+          bb[1] = zc;
+          bb[2] = grid;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  scd_status st = scd_batch_set_tile(b, bb[0], bb[1], bb[2]);
+  if (st) return st;
+  for (int j = 0; j < 3; ++j) best[j] = bb[j];
+  *best_ms = bms;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << "{\"key\": \"" << key << "\", \"best\": [" << bb[0] << ", " << bb[1] << ", " << bb[2]
+      << "], \"ms\": " << std::setprecision(17) << bms << "}\n";
+  }
   return SCD_OK;
 }
 

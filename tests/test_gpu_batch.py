@@ -20,14 +20,14 @@ def _members(dtype):
     return cases
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_batch_equals_sequential(dtype):
-    announce(f"batch: 3 uneven members, {dtype}, 40 steps")
+@pytest.mark.parametrize("dtype,grid", [("f64", 64), ("f32", 64), ("f32", 0)])
+def test_batch_equals_sequential(dtype, grid):
+    announce(f"batch: 3 uneven members, {dtype}, grid {grid}, 40 steps")
     cases = _members(dtype)
     s = torch.cuda.Stream()
     B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
     var = [i for i, r in enumerate(scd.tile_list()) if r[2] == 2][0]  # a species-split variant
-    B.set_tile(var, 8, 64)
+    B.set_tile(var, 8, grid)
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     B.step(20)
@@ -61,3 +61,27 @@ def test_autotune_keeps_results(tmp_path):
     R.init_equilibrium(c["rho_a"], c["rho_b"])
     R.step(30)
     assert torch.max(torch.abs(L.get_state().cpu() - R.get_state().cpu())).item() <= 1e-13
+
+
+def test_batch_autotune_then_default_tiles_match_sequential(tmp_path):
+    """After the batch autotuner (which advances the members) a fresh start
+    with the chosen tile equals the members stepped one by one with it."""
+    cases = _members("f32")
+    s = torch.cuda.Stream()
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    cache = str(tmp_path / "btune.jsonl")
+    best, ms = B.autotune(2, cache)
+    assert ms > 0 and len(best) == 3
+    assert B.autotune(2, cache) == (best, ms)  # served from the cache
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    B.step(24)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        L = scd.Lattice(c["params"], c["solid"])
+        L.set_tile(best[0], min(best[1], c["params"]["nz"]))
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(24)
+        assert torch.equal(B.view(i).get_state().cpu(), L.get_state().cpu()), i
