@@ -140,17 +140,37 @@ struct scd_lattice {
 
 namespace {
 
-// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet): FP64
-// runs best as the species-split z-march with streaming stores, FP32 with
-// both population sets in registers and shorter z-chunks.
+// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet): both
+// precisions run best as the species-split z-march that issues all loads of
+// a plane at once, FP64 on 32 x 4 tiles with one wave per SIMD (its register
+// set does not fit two), FP32 on 32 x 8 tiles.
 int default_variant(int dtype) {
-  int v = dtype == SCD_F64 ? variant_find(32, 8, 3, 2) : variant_find(32, 8, 0, 1);
+  int v = dtype == SCD_F64 ? variant_find(32, 4, 5, 1) : variant_find(32, 8, 5, 2);
   return v < 0 ? 0 : v;
+}
+
+int device_cus() {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus > 0 ? cus : 256;
+}
+
+// z-chunk: the longest of 32, 16, 8, 4 planes that still gives every compute
+// unit a workgroup (long chunks re-pull fewer halo planes).
+int default_zc(const scd_params& p, int variant) {
+  int tx, ty, var, wpe;
+  variant_at(variant, &tx, &ty, &var, &wpe);
+  const long cols = (long)((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
+  const int cus = device_cus();
+  for (int zc : {32, 16, 8})
+    if (cols * ((p.nz + zc - 1) / zc) >= cus) return std::min(zc, p.nz);
+  return std::min(4, p.nz);
 }
 
 void default_tile(scd_lattice* h) {
   h->variant = default_variant(h->p.dtype);
-  h->zc = std::min(h->p.dtype == SCD_F64 ? 16 : 8, h->p.nz);
+  h->zc = default_zc(h->p, h->variant);
   h->remap = 1;
 }
 
@@ -831,7 +851,7 @@ scd_status batch_upload(scd_batch* b) {
 // short chunks cost more than the lost parallelism of long ones, so the
 // batch marches 32 planes per item; one workgroup per item (grid 0).
 void batch_default_tile(int dtype, int* variant, int* zc, int* grid) {
-  *variant = dtype == SCD_F64 ? default_variant(dtype) : variant_find(64, 4, 0, 1);
+  *variant = variant_find(64, 4, 0, 1);
   if (*variant < 0) *variant = default_variant(dtype);
   *zc = 32;
   *grid = 0;
@@ -1003,9 +1023,7 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
     *best_ms = cms;
     return SCD_OK;
   }
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int cus = device_cus();
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

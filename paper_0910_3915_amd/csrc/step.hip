@@ -187,50 +187,69 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   real ncur[38], nnext[38];
   bool solid_cur = true, solid_next = true;
 
+  // Link masks of the plane about to be pulled, loaded one plane ahead so
+  // that the population loads of a plane never wait for its masks.
+  uint32_t lbi, lbh[T::HPT];
+  auto load_links = [&](int zr, uint32_t& li, uint32_t(&lh)[T::HPT]) {
+    const int z = wrap_index(zr, nz);
+    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h)
+      lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
+  };
+  load_links(za - 1, lbi, lbh);
+
   // e of plane zr (raw, may lie outside [0, nz)) into ring slot zr & 3; the
-  // interior populations are kept in nout when keep is set.  The halo is
-  // pulled first, so that its loads are never in flight together with both
-  // population sets of the register variant.
+  // interior populations are kept in nout when keep is set.  All loads of
+  // the plane (halo and interior) are issued before any of them is used,
+  // then the masks of plane zr + 1 are requested.
   auto plane = [&](int zr, bool keep, real(&nout)[38], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
     E2<real>* slot = lds + (zr & 3) * T::P;
+    real hm[T::HPT][38];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      if (!(lbh[h] & SELF_SOLID)) pull38(L.src, N, i, hx[h], hy[h], zs, nx, ny, lbh[h], hm[h]);
+    }
+    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+    solid_out = (lbi & SELF_SOLID) != 0;
+    real m[38];
+    if (!solid_out) {
+      if (keep) pull38(L.src, N, i, xs, ys, zs, nx, ny, lbi, nout);
+      else pull38(L.src, N, i, xs, ys, zs, nx, ny, lbi, m);
+    }
+    uint32_t nli, nlh[T::HPT];
+    load_links(zr + 1, nli, nlh);
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
       if (!hval[h]) continue;
-      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
-      const uint32_t lb = L.links[i];
-      E2<real> e;
-      if (lb & SELF_SOLID) {
-        e = ewall;
-      } else {
-        real ra, rb;
-        pull_density(L.src, N, i, hx[h], hy[h], zs, nx, ny, lb, ra, rb);
+      E2<real> e = ewall;
+      if (!(lbh[h] & SELF_SOLID)) {
+        real ra = 0, rb = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) { ra += hm[h][k]; rb += hm[h][Q + k]; }
         e = fluid_e(L.ph, ra, rb);
       }
       slot[hpos[h]] = e;
     }
-    phase_fence();
-    {
-      const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
-      const uint32_t lb = L.links[i];
-      E2<real> e;
-      solid_out = (lb & SELF_SOLID) != 0;
-      if (solid_out) {
-        e = ewall;
-      } else if (keep) {
-        pull38(L.src, N, i, xs, ys, zs, nx, ny, lb, nout);
-        real ra = 0, rb = 0;
+    E2<real> e = ewall;
+    if (!solid_out) {
+      real ra = 0, rb = 0;
+      if (keep) {
 #pragma unroll
         for (int k = 0; k < Q; ++k) { ra += nout[k]; rb += nout[Q + k]; }
-        e = fluid_e(L.ph, ra, rb);
       } else {
-        real ra, rb;
-        pull_density(L.src, N, i, xs, ys, zs, nx, ny, lb, ra, rb);
-        e = fluid_e(L.ph, ra, rb);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) { ra += m[k]; rb += m[Q + k]; }
       }
-      slot[pos] = e;
+      e = fluid_e(L.ph, ra, rb);
     }
+    slot[pos] = e;
+    lbi = nli;
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) lbh[h] = nlh[h];
   };
 
   if constexpr (VAR == VAR_REG) {
@@ -322,7 +341,7 @@ struct SplitTile {
   static_assert(TX % 32 == 0, "a half-wave covers 32 nodes of one row");
 };
 
-template <typename real, int TX, int TY, bool NT_STORE>
+template <typename real, int TX, int TY, bool NT_STORE, bool JOINT>
 __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, int by, int za,
                                                 int zb, real* __restrict__ lds) {
   auto store = [](char* base, uint32_t off, real v) {
@@ -370,19 +389,43 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   real ncur[19], nnext[19];
   bool solid_cur = true, solid_next = true;
 
-  auto plane = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
+  // Link masks of the plane about to be pulled, loaded one plane ahead so
+  // that the population loads of a plane never wait for its masks.
+  uint32_t lbi, lbh[T::HPT];
+  auto load_links = [&](int zr, uint32_t& li, uint32_t(&lh)[T::HPT]) {
+    const int z = wrap_index(zr, nz);
+    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h)
+      lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
+  };
+  load_links(za - 1, lbi, lbh);
+
+  // Parameters of the e values, held in registers for the whole march.
+  const real gab = L.ph.gab;
+  const int psi_form = L.ph.psi_form;
+  const real ew0 = L.ph.gw[1] * L.ph.psiw[0];  // e written by a wall thread of species 0
+  const real ew1 = L.ph.gw[0] * L.ph.psiw[1];  // ... of species 1
+  auto e_of = [&](int sp, bool wall, real rho) {
+    return wall ? (sp ? ew1 : ew0) : gab * psi_of(psi_form, rho);
+  };
+
+  // The halo of plane zr is pulled and reduced first, then the interior
+  // (a fence between them bounds the live registers: the interior set is
+  // pulled while the collided plane's set is still held); the masks of
+  // plane zr + 1 are requested behind the interior loads.
+  auto plane_fenced = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
       if (!hval[h]) continue;
       const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
-      const uint32_t lb = L.links[i];
-      const bool wall = lb & SELF_SOLID;
+      const bool wall = lbh[h] & SELF_SOLID;
       real r = 0;
       if (!wall) {
         real m[19];
-        pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lb, m);
+        pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lbh[h], m);
 #pragma unroll
         for (int k = 0; k < Q; ++k) r += m[k];
       }
@@ -390,22 +433,77 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
     }
     phase_fence();
     const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
-    const uint32_t lb = L.links[i];
-    solid_out = (lb & SELF_SOLID) != 0;
+    solid_out = (lbi & SELF_SOLID) != 0;
+    real m[19];
+    if (!solid_out) {
+      if (keep) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, nout);
+      else pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, m);
+    }
+    load_links(zr + 1, lbi, lbh);
     real r = 0;
     if (!solid_out) {
       if (keep) {
-        pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, nout);
 #pragma unroll
         for (int k = 0; k < Q; ++k) r += nout[k];
       } else {
-        real m[19];
-        pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, m);
 #pragma unroll
         for (int k = 0; k < Q; ++k) r += m[k];
       }
     }
     ring(zr, 1 - a)[pos] = e_from(L.ph, a, solid_out, r);
+  };
+
+  // All loads of plane zr are issued before any is used: the interior set,
+  // then the halo, then the masks of plane zr + 1.
+  auto plane_joint = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
+    int zs[3];
+    axis3(wrap_index(zr, nz), nz, zs);
+    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+    solid_out = (lbi & SELF_SOLID) != 0;
+    real m[19];
+    if (!solid_out) {
+      if (keep) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, nout);
+      else pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, m);
+    }
+    real hm[T::HPT][19];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      const int ih = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
+      if (!(lbh[h] & SELF_SOLID))
+        pull19(L.src, N, hsp[h], ih, hx[h], hy[h], zs, nx, ny, lbh[h], hm[h]);
+    }
+    uint32_t nli, nlh[T::HPT];
+    load_links(zr + 1, nli, nlh);
+    real r = 0;
+    if (!solid_out) {
+      if (keep) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += nout[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) r += m[k];
+      }
+    }
+    ring(zr, 1 - a)[pos] = e_of(a, solid_out, r);
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      const bool wall = lbh[h] & SELF_SOLID;
+      real rh = 0;
+      if (!wall) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) rh += hm[h][k];
+      }
+      ring(zr, 1 - hsp[h])[hpos[h]] = e_of(hsp[h], wall, rh);
+    }
+    lbi = nli;
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) lbh[h] = nlh[h];
+  };
+
+  auto plane = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
+    if constexpr (JOINT) plane_joint(zr, keep, nout, solid_out);
+    else plane_fenced(zr, keep, nout, solid_out);
   };
 
   const Phys<real>& ph = L.ph;
@@ -654,10 +752,13 @@ __device__ __forceinline__ bool tile_of_block(int b, int total, int remap, int g
 constexpr int VAR_SPLIT = 2;     // species-split z-march
 constexpr int VAR_SPLIT_NT = 3;  // the same with streaming stores
 constexpr int VAR_PIPE = 4;      // software-pipelined species split, streaming stores
+constexpr int VAR_JOINT = 5;     // species split, streaming stores, all loads of a plane
+                                 // (interior and halo) issued before any is used
 
 template <typename real, int TX, int TY, int VAR>
 struct StepShape {
-  static constexpr bool SPLIT = VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE;
+  static constexpr bool SPLIT =
+      VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT;
   static constexpr int THREADS = SPLIT ? 2 * TX * TY : TX * TY;
   static constexpr int LDS_REALS = SPLIT ? 8 * SplitTile<TX, TY>::P : 8 * Tile<TX, TY>::P;
 };
@@ -666,9 +767,11 @@ template <typename real, int TX, int TY, int VAR>
 __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, int za, int zb,
                                          real* lds) {
   if constexpr (VAR == VAR_SPLIT)
-    step_tile_split<real, TX, TY, false>(L, bx, by, za, zb, lds);
+    step_tile_split<real, TX, TY, false, false>(L, bx, by, za, zb, lds);
   else if constexpr (VAR == VAR_SPLIT_NT)
-    step_tile_split<real, TX, TY, true>(L, bx, by, za, zb, lds);
+    step_tile_split<real, TX, TY, true, false>(L, bx, by, za, zb, lds);
+  else if constexpr (VAR == VAR_JOINT)
+    step_tile_split<real, TX, TY, true, true>(L, bx, by, za, zb, lds);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -841,8 +944,8 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
 // the minimum waves per SIMD the register allocation must allow.
 #define SCD_VARIANTS(X)                                                                   \
   X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
-  X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 4, 2) X(64, 4, 4, 2) X(32, 8, 4, 2) \
-  X(64, 2, 4, 2) X(32, 4, 4, 3)
+  X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 5, 1) X(32, 4, 5, 2) X(32, 8, 5, 2) \
+  X(64, 4, 5, 2)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},
