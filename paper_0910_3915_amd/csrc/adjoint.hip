@@ -11,9 +11,9 @@
 //      E^a = dL/dj^a, and accumulate the parameter gradient;
 //   2. per fluid node: add the transposed force stencil, i.e. the gather
 //      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) into D;
-//   3. per node: transposed streaming with bounce-back, a gather of
-//      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k from x + c_k (or from x
-//      itself on the opposite velocity next to a wall).
+//   3. per node: transposed streaming with bounce-back, as a push of
+//      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k to x - c_k (or to the
+//      node itself on the opposite velocity next to a wall).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -212,7 +212,13 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
   }
 }
 
-// lambda_j(x) = dL/dn_j(x + c_j) if x + c_j is fluid, else dL/dn_{opp j}(x)
+// Transposed streaming, as a push from every fluid node y:
+//   mu_k(y) = D(y) + E(y) . c_k + (1 - 1/tau) lambda'_k(y)   (= dL/dn_k(y))
+// goes to lambda_k(y - c_k) when y - c_k is fluid (the forward step pulled
+// n_k(y) from C_k(y - c_k)), and mu_{opp k}(y) goes to lambda_k(y) itself
+// when y + c_k is a wall (the forward step bounced C_k(y) back into
+// n_{opp k}(y)).  Every entry of lambda is written exactly once, and all
+// loads are of the node's own values.
 template <typename real>
 __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__ links, int nx,
                                                     int ny, int nz, Phys<real> ph,
@@ -233,17 +239,24 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const bool wall = (lb >> k) & 1u;
-      const int y = wall ? i : nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
-      const int kk = wall ? OPP[k] : k;
-      const int sx = wall ? -CX[k] : CX[k], sy = wall ? -CY[k] : CY[k], sz = wall ? -CZ[k] : CZ[k];
+    for (int a = 0; a < 2; ++a) {
+      const real D = df[(size_t)a * N + i];
+      const real Ex = ef[(size_t)(a * 3 + 0) * N + i];
+      const real Ey = ef[(size_t)(a * 3 + 1) * N + i];
+      const real Ez = ef[(size_t)(a * 3 + 2) * N + i];
+      const real keep = real(1) - ph.inv_tau[a];
+      real mu[Q];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const real mu = df[(size_t)a * N + y] + ef[(size_t)(a * 3 + 0) * N + y] * sx +
-                        ef[(size_t)(a * 3 + 1) * N + y] * sy + ef[(size_t)(a * 3 + 2) * N + y] * sz +
-                        (real(1) - ph.inv_tau[a]) * lam[(size_t)(a * Q + kk) * N + y];
-        out[(size_t)(a * Q + k) * N + i] = mu;
+      for (int k = 0; k < Q; ++k)
+        mu[k] = D + Ex * CX[k] + Ey * CY[k] + Ez * CZ[k] + keep * lam[(size_t)(a * Q + k) * N + i];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (!((lb >> OPP[k]) & 1u)) {  // y - c_k is fluid: it pulled n_k(y)
+          const int x = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+          out[(size_t)(a * Q + k) * N + x] = mu[k];
+        }
+        if ((lb >> k) & 1u)  // y + c_k is a wall: n_{opp k}(y) came from C_k(y)
+          out[(size_t)(a * Q + k) * N + i] = mu[OPP[k]];
       }
     }
   }
