@@ -262,6 +262,11 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
   }
 }
 
+// Workgroups of the local pass (grid-stride over the nodes).  The FP64
+// kernel holds one wave per SIMD (its register set), so more workgroups
+// than two per CU only queue; the FP32 kernel fits several waves per SIMD.
+static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : ADJ_BLOCKS; }
+
 template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                             const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
@@ -271,8 +276,8 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
   const size_t N = (size_t)nx * ny * nz;
   hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_local<real>, dim3(ADJ_BLOCKS), dim3(256), 0, s, C, lam_in, links, rhof,
-                     nx, ny, nz, ph, qf, df, ef, partials);
+  hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, C,
+                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny, nz,
                      ph, qf, df);
@@ -298,7 +303,8 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
                          ny, nz, ph, (float*)rho_field, (float*)q_field, (float*)d_field,
                          (float*)e_field, partials, dparams_dev, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum5, dim3(1), dim3(256), 0, s, partials, ADJ_BLOCKS, dparams_dev, acc);
+  hipLaunchKernelGGL(k_sum5, dim3(1), dim3(256), 0, s, partials, adj_local_grid(dtype == 0 ? 8 : 4),
+                     dparams_dev, acc);
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
                           void* lambda, hipStream_t s);
 
 // adjoint.hip
-constexpr int ADJ_BLOCKS = 512;
+constexpr int ADJ_BLOCKS = 2048;
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
                           void* rho_field, void* q_field, void* d_field, void* e_field,
