@@ -92,6 +92,9 @@ def lib():
         L.ora_adjoint_step.argtypes = [vp, dp, dp, dp]
         L.ora_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.ora_tables.argtypes = [ctypes.POINTER(ctypes.c_int32), dp, ctypes.POINTER(ctypes.c_int32)]
+        L.ora_pressure_tensor.argtypes = [vp, dp]
+        L.ora_surface_tension_z.restype = ctypes.c_double
+        L.ora_surface_tension_z.argtypes = [vp, dp]
         _lib = L
     return _lib
 
@@ -212,6 +215,18 @@ class Lattice:
         F = np.zeros(self.shape + (2, 3))
         lib().ora_force(self._h, _dp(r), _dp(F))
         return F
+
+    def pressure_tensor(self):
+        """(nz, ny, nx, 6): xx, yy, zz, xy, xz, yz; zero at solid nodes."""
+        P = np.zeros(self.shape + (6,))
+        lib().ora_pressure_tensor(self._h, _dp(P))
+        return P
+
+    def surface_tension_z(self):
+        """(sum over planes of <P_zz - (P_xx + P_yy)/2>, plane profile)."""
+        prof = np.zeros(self.shape[0])
+        g = lib().ora_surface_tension_z(self._h, _dp(prof))
+        return g, prof
 
     def contact_angle(self, cfg):
         out = OraCa()

@@ -337,6 +337,75 @@ void ora_step(ora_lattice* L, int64_t nsteps) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pressure tensor of Sec. 4.1 at the fluid nodes, from the post-stream
+ * populations n of the current state (the distribution at time t that the
+ * collision acts on):
+ *   P_ij(x) = sum_a sum_k (c_ki - u_i)(c_kj - u_j) n_k^a(x)
+ *           + 1/2 sum_k W_k c_ki c_kj [psi^A(x) G^A(y) psi^B(y) + psi^B(x) G^B(y) psi^A(y)]
+ * with y = x + c_k and u = sum_a j^a / sum_a rho^a the velocity of the
+ * fluid.  The paper's second term sums over the ordered species pairs with a
+ * prefactor 1/4; both orderings give the same bracket, hence 1/2.  Its pair
+ * factor (x - x')^2 is read as the dyad (x - x')_i (x - x')_j of a tensor.
+ * Wall neighbours enter as in the force (Sec. 2 wall model): their content
+ * through psi and the coupling g_wall^a.                                    */
+void ora_pressure_tensor(ora_lattice* L, double* P) {
+  forward_fields(L, L->C);
+  static const int PI[6] = {0, 1, 2, 0, 0, 1}, PJ[6] = {0, 1, 2, 1, 2, 2};
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < L->nz; ++z)
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) {
+        size_t i = node_at(L, x, y, z);
+        double* out = P + i * 6;
+        for (int c = 0; c < 6; ++c) out[c] = 0.0;
+        if (L->solid[i]) continue;
+        double R = L->rho[i * 2] + L->rho[i * 2 + 1];
+        double u[3];
+        for (int d = 0; d < 3; ++d) u[d] = (L->j[i * 6 + d] + L->j[i * 6 + 3 + d]) / R;
+        for (int c = 0; c < 6; ++c) {
+          double kin = 0.0, inter = 0.0;
+          for (int k = 0; k < ORA_Q; ++k) {
+            double nk = L->n[i * 38 + k] + L->n[i * 38 + ORA_Q + k];
+            kin += (CV[k][PI[c]] - u[PI[c]]) * (CV[k][PJ[c]] - u[PJ[c]]) * nk;
+          }
+          for (int k = 1; k < ORA_Q; ++k) {
+            size_t yy = node_at(L, x + CV[k][0], y + CV[k][1], z + CV[k][2]);
+            double br = L->psi[i * 2] * coupling(L, 0, yy) * L->psi[yy * 2 + 1] +
+                        L->psi[i * 2 + 1] * coupling(L, 1, yy) * L->psi[yy * 2];
+            inter += weight_of(L, k) * CV[k][PI[c]] * CV[k][PJ[c]] * br;
+          }
+          out[c] = kin + 0.5 * inter;
+        }
+      }
+}
+
+/* Eq. (gammaMechDef) on the lattice for interfaces normal to z: the sum over
+ * the planes z that hold fluid of the plane mean (over its fluid nodes) of
+ * P_N - P_T = P_zz - (P_xx + P_yy) / 2.  A periodic box with two interfaces
+ * holds twice the surface tension.  profile (nz values, or NULL): the plane
+ * means, 0 for planes without fluid.                                       */
+double ora_surface_tension_z(ora_lattice* L, double* profile) {
+  double* P = (double*)malloc(L->N * 6 * sizeof(double));
+  ora_pressure_tensor(L, P);
+  double total = 0.0;
+  size_t A = (size_t)L->nx * L->ny;
+  for (int z = 0; z < L->nz; ++z) {
+    double s = 0.0;
+    size_t cnt = 0;
+    for (size_t i = (size_t)z * A; i < (size_t)(z + 1) * A; ++i) {
+      if (L->solid[i]) continue;
+      s += P[i * 6 + 2] - 0.5 * (P[i * 6 + 0] + P[i * 6 + 1]);
+      ++cnt;
+    }
+    double m = cnt ? s / (double)cnt : 0.0;
+    if (profile) profile[z] = m;
+    total += m;
+  }
+  free(P);
+  return total;
+}
+
+/* ------------------------------------------------------------------------ */
 void ora_density(const ora_lattice* L, double* rho) {
   for (size_t i = 0; i < L->N; ++i)
     for (int a = 0; a < 2; ++a) {

@@ -112,6 +112,14 @@ void ora_stream(const ora_lattice* L, const double* in, double* out);
    F[node*6 + a*3 + d] */
 void ora_force(const ora_lattice* L, const double* rho, double* F);
 
+/* Pressure tensor (Sec. 4.1) of the current state at every node:
+   P[node*6 + {xx, yy, zz, xy, xz, yz}], zero at solid nodes. */
+void ora_pressure_tensor(ora_lattice* L, double* P);
+/* Surface tension integral (Eq. gammaMechDef) for interfaces normal to z:
+   sum over planes of the plane mean of P_zz - (P_xx + P_yy)/2 over fluid
+   nodes; profile (nz values) may be NULL. */
+double ora_surface_tension_z(ora_lattice* L, double* profile);
+
 /* contact angle of the current state; returns 0, or -4 when no droplet */
 int ora_contact_angle(const ora_lattice* L, const ora_ca_cfg* cfg, ora_ca* out);
 /* same, on a given order-parameter field phi (one value per node); solid
