@@ -72,6 +72,8 @@ _PROTOS = {
     "scd_set_state": [_VP, _VP, _I64],
     "scd_fill_state": [_VP, _D],
     "scd_density": [_VP, _VP],
+    "scd_pressure_tensor": [_VP, _VP],
+    "scd_surface_tension_z": [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "scd_observables": [_VP, ctypes.POINTER(ScdObs)],
     "scd_contact_angle": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
     "scd_ca_seed": [_VP, ctypes.POINTER(ScdCaCfg), _D, _VP],
@@ -267,6 +269,24 @@ class Lattice:
         check(lib().scd_density(self.h, _ptr(out)))
         self._before_torch()
         return out
+
+    def pressure_tensor(self):
+        """(6, nz, ny, nx) FP64: xx, yy, zz, xy, xz, yz (zero at wall nodes)."""
+        out = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
+        self._after_torch()
+        check(lib().scd_pressure_tensor(self.h, _ptr(out)))
+        self._before_torch()
+        return out
+
+    def surface_tension_z(self, scratch=None):
+        """(sum over planes of <P_zz - (P_xx + P_yy)/2>, plane profile)."""
+        if scratch is None:
+            scratch = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
+        g = _D()
+        prof = (_D * self.shape[0])()
+        self._after_torch()
+        check(lib().scd_surface_tension_z(self.h, _ptr(scratch), ctypes.byref(g), prof))
+        return g.value, list(prof)
 
     def observables(self, raise_nonfinite=True):
         o = ScdObs()

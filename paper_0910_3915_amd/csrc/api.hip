@@ -46,7 +46,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t real_size(int dtype) { return dtype == SCD_F64 ? 8 : 4; }
 
 struct WorkLayout {
-  size_t links, partials, result, phi, ca, adj_partials, adj_dparams, rho, q, d, e, total;
+  size_t links, partials, result, phi, ca, planes, rho, adj_partials, adj_dparams, q, d, e, total;
 };
 
 WorkLayout work_layout(const scd_params* p) {
@@ -60,10 +60,11 @@ WorkLayout work_layout(const scd_params* p) {
   w.result = take(16 * 8);
   w.phi = take((2 * (size_t)p->nx * p->ny + p->nz) * 8);
   w.ca = take(CA_SLOTS * 8);
+  w.planes = take((size_t)p->nz * 8);  // plane means of the tension integrand
+  w.rho = take(2 * N * rs);            // post-stream densities (pressure, adjoint)
   if (p->flags & SCD_WITH_ADJOINT) {
     w.adj_partials = take((size_t)ADJ_BLOCKS * RED_STRIDE * 8);
     w.adj_dparams = take(16 * 8);  // [0, 8): last step, [8, 16): accumulator
-    w.rho = take(2 * N * rs);
     w.q = take(6 * N * rs);
     w.d = take(2 * N * rs);
     w.e = take(6 * N * rs);
@@ -337,6 +338,30 @@ scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step) {
 scd_status scd_fill_state(scd_lattice* h, double value) {
   if (!h) return fail(SCD_EINVAL, "NULL handle");
   HIPCHK(launch_fill(h->p.dtype, h->pop[h->cur], 2 * Q * h->N, value, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_pressure_tensor(scd_lattice* h, double* d_P) {
+  if (!h || !d_P) return fail(SCD_EINVAL, "NULL argument");
+  HIPCHK(launch_pressure(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz, h->ph,
+                         h->wd(h->wl.rho), d_P, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
+                                 double* h_profile) {
+  if (!h || !d_P || !h_gamma) return fail(SCD_EINVAL, "NULL argument");
+  scd_status st = scd_pressure_tensor(h, d_P);
+  if (st) return st;
+  double* planes = (double*)h->wd(h->wl.planes);
+  HIPCHK(launch_plane_tension(h->links(), h->p.nx, h->p.ny, h->p.nz, d_P, planes, h->stream));
+  std::vector<double> prof(h->p.nz);
+  HIPCHK(hipMemcpyAsync(prof.data(), planes, prof.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double total = 0.0;  // planes summed in order z = 0, 1, ...
+  for (int z = 0; z < h->p.nz; ++z) total += prof[z];
+  *h_gamma = total;
+  if (h_profile) std::copy(prof.begin(), prof.end(), h_profile);
   return SCD_OK;
 }
 

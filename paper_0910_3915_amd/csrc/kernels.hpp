@@ -64,6 +64,10 @@ struct CaDev {
 hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
                                 int nz, CaDev cfg, double* phi_scratch, double* result,
                                 hipStream_t s);
+hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                           int nz, const PhysD& ph, void* rho, double* P, hipStream_t s);
+hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
+                                double* profile, hipStream_t s);
 hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,
                           const double* phi_scratch, const double* result, double dL_dtheta,
                           void* lambda, hipStream_t s);

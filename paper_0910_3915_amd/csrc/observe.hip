@@ -392,4 +392,113 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// Pressure tensor (Sec. 4.1) at every node from the post-stream populations
+// of the current state; rho: their densities at every node (2 N values).
+//   P_ij = sum_a sum_k (c_ki - u_i)(c_kj - u_j) n_k^a
+//        + 1/2 sum_k W_k c_ki c_kj [psi^A G^A(y) psi^B(y) + psi^B G^B(y) psi^A(y)]
+// with y = x + c_k and u = sum_a j^a / sum_a rho^a; the paper's sum over the
+// two ordered species pairs with prefactor 1/4 gives the 1/2, its pair factor
+// is the dyad of (x - x'), and wall neighbours carry their content and
+// g_wall^a as in the force.  Output P[c * N + i] (FP64), c = xx, yy, zz, xy,
+// xz, yz; zero at wall nodes.
+template <typename real>
+__global__ __launch_bounds__(256) void k_pressure(const real* __restrict__ pop,
+                                                  const uint32_t* __restrict__ links,
+                                                  const real* __restrict__ rho, int nx, int ny,
+                                                  int nz, Phys<real> ph, double* __restrict__ P) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    double out[6] = {0, 0, 0, 0, 0, 0};
+    if (!(lb & SELF_SOLID)) {
+      int xs[3], ys[3], zs[3];
+      axis3(i % nx, nx, xs);
+      axis3((i / nx) % ny, ny, ys);
+      axis3(i / (nx * ny), nz, zs);
+      real n[38];
+      pull38(pop, N, i, xs, ys, zs, nx, ny, lb, n);
+      double R = 0, j[3] = {0, 0, 0}, m[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const double f = (double)n[k] + (double)n[Q + k];
+        R += f;
+        j[0] += CX[k] * f; j[1] += CY[k] * f; j[2] += CZ[k] * f;
+        m[0] += CX[k] * CX[k] * f; m[1] += CY[k] * CY[k] * f; m[2] += CZ[k] * CZ[k] * f;
+        m[3] += CX[k] * CY[k] * f; m[4] += CX[k] * CZ[k] * f; m[5] += CY[k] * CZ[k] * f;
+      }
+      const double u[3] = {j[0] / R, j[1] / R, j[2] / R};
+      // sum_k (c - u)_i (c - u)_j f = M_ij - u_i J_j - J_i u_j + R u_i u_j
+      const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        out[c] = m[c] - u[ci[c]] * j[cj[c]] - j[ci[c]] * u[cj[c]] + R * u[ci[c]] * u[cj[c]];
+      const double pA = psi_of(ph.psi_form, (double)rho[i]);
+      const double pB = psi_of(ph.psi_form, (double)rho[(size_t)N + i]);
+      double t[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        const bool wall = (lb >> k) & 1u;
+        double qA = ph.psiw[0], qB = ph.psiw[1], gA = ph.gw[0], gB = ph.gw[1];
+        if (!wall) {
+          const int y = nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
+          qA = psi_of(ph.psi_form, (double)rho[y]);
+          qB = psi_of(ph.psi_form, (double)rho[(size_t)N + y]);
+          gA = gB = ph.gab;
+        }
+        const double w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const double br = w * (pA * gA * qB + pB * gB * qA);
+        t[0] += CX[k] * CX[k] * br; t[1] += CY[k] * CY[k] * br; t[2] += CZ[k] * CZ[k] * br;
+        t[3] += CX[k] * CY[k] * br; t[4] += CX[k] * CZ[k] * br; t[5] += CY[k] * CZ[k] * br;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c] += 0.5 * t[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) P[(size_t)c * N + i] = out[c];
+  }
+}
+
+// One workgroup per plane z: mean over its fluid nodes of P_zz - (P_xx +
+// P_yy) / 2 (Eq. gammaMechDef's integrand for interfaces normal to z), 0 for
+// a plane without fluid.
+__global__ __launch_bounds__(256) void k_plane_tension(const uint32_t* __restrict__ links, int nx,
+                                                       int ny, int nz,
+                                                       const double* __restrict__ P,
+                                                       double* __restrict__ profile) {
+  __shared__ double sh[2 * 16];
+  const int N = nx * ny * nz, A = nx * ny;
+  const int z = blockIdx.x;
+  double v[2] = {0, 0};
+  for (int t = threadIdx.x; t < A; t += blockDim.x) {
+    const int i = z * A + t;
+    if (links[i] & SELF_SOLID) continue;
+    v[0] += P[(size_t)2 * N + i] - 0.5 * (P[i] + P[(size_t)N + i]);
+    v[1] += 1.0;
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) profile[z] = v[1] > 0 ? v[0] / v[1] : 0.0;
+}
+
+hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                           int nz, const PhysD& ph, void* rho, double* P, hipStream_t s) {
+  hipError_t e = launch_stream_density(dtype, pop, links, rho, nx, ny, nz, s);
+  if (e != hipSuccess) return e;
+  const size_t N = (size_t)nx * ny * nz;
+  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_pressure<double>, dim3(blocks), dim3(256), 0, s, (const double*)pop, links,
+                       (const double*)rho, nx, ny, nz, ph, P);
+  else
+    hipLaunchKernelGGL(k_pressure<float>, dim3(blocks), dim3(256), 0, s, (const float*)pop, links,
+                       (const float*)rho, nx, ny, nz, phys_cast<float>(ph), P);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
+                                double* profile, hipStream_t s) {
+  hipLaunchKernelGGL(k_plane_tension, dim3(nz), dim3(256), 0, s, links, nx, ny, nz, P, profile);
+  return hipGetLastError();
+}
+
 }  // namespace scd

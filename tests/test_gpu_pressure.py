@@ -1,0 +1,67 @@
+"""Parity of the HIP pressure tensor and planar surface tension (Sec. 4.1,
+Eq. gammaMechDef) with the oracle on the same states: a relaxing lamella,
+wall slabs (wall neighbours in the interaction term), a droplet on walls,
+the exponential pseudopotential and weighted stencil, and FP32 states.
+FP64 within 1e-12 relative to the largest component; FP32 states within
+1e-6 (the GPU forms the densities of an FP32 state in FP32)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_0910_3915_amd as scd
+import workloads as W
+from gpu_helpers import announce, gpu_state_as_oracle
+
+
+def _lamella(n=8, nz=64, g=0.1, **kw):
+    p = W.params(n, n, nz, g, **kw)
+    z = np.arange(nz)[:, None, None] * np.ones((1, n, n))
+    inside = (z >= nz // 4) & (z < 3 * nz // 4)
+    return p, np.zeros((nz, n, n), np.uint8), np.where(inside, 0.7, 0.04), np.where(inside, 0.04, 0.7)
+
+
+def _slab(n=8, nz=48, wall=16, g=0.1, delta=-0.2):
+    p = W.params(n, n, nz, g, rho_wall=W.asymmetric_wall(delta))
+    solid = np.zeros((nz, n, n), np.uint8)
+    solid[:wall] = 1
+    ra = np.full((nz, n, n), 0.7)
+    rb = np.full((nz, n, n), 0.04)
+    ra[:wall] = rb[:wall] = 0.0
+    return p, solid, ra, rb
+
+
+def _droplet():
+    c = W.droplet_case(24, 20, 16, 6.0, 0.12, 0.2)
+    return c["params"], c["solid"], c["rho_a"], c["rho_b"]
+
+
+CASES = {
+    "lamella": lambda: _lamella(),
+    "lamella_exp_weighted": lambda: _lamella(g=0.2, psi=1, w_axis=1.2, w_diag=0.9),
+    "wall_slab": lambda: _slab(),
+    "droplet": lambda: _droplet(),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pressure_and_tension_match_oracle(name, dtype):
+    announce(f"pressure parity: {name} {dtype}")
+    p, solid, ra, rb = CASES[name]()
+    p = dict(p, dtype=dtype)
+    L = scd.Lattice(p, solid)
+    L.init_equilibrium(ra, rb)
+    L.step(300)
+    P = L.pressure_tensor().cpu().numpy()  # (6, nz, ny, nx)
+    gam, prof = L.surface_tension_z()
+    Lo = O.Lattice(dict(p, dtype="f64"), solid)
+    Lo.set_state(gpu_state_as_oracle(L))
+    Po = np.moveaxis(Lo.pressure_tensor(), -1, 0)
+    go, profo = Lo.surface_tension_z()
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    scale = np.max(np.abs(Po))
+    assert np.max(np.abs(P - Po)) <= tol * scale
+    assert np.allclose(prof, profo, rtol=0, atol=tol * scale)
+    assert abs(gam - go) <= tol * scale * len(prof)
