@@ -93,6 +93,10 @@ def lib():
         L.ora_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.ora_tables.argtypes = [ctypes.POINTER(ctypes.c_int32), dp, ctypes.POINTER(ctypes.c_int32)]
         L.ora_pressure_tensor.argtypes = [vp, dp]
+        L.ora_young_angle.restype = ctypes.c_double
+        L.ora_young_angle.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.ora_huang_angle.restype = ctypes.c_double
+        L.ora_huang_angle.argtypes = [ctypes.POINTER(OraParams), ctypes.c_double, ctypes.c_double]
         L.ora_surface_tension_z.restype = ctypes.c_double
         L.ora_surface_tension_z.argtypes = [vp, dp]
         _lib = L
@@ -257,6 +261,15 @@ class Lattice:
         dp = np.zeros(5)
         lib().ora_adjoint_step(self._h, _dp(st), _dp(lm), _dp(dp))
         return lm, dp
+
+
+def young_angle(gamma_sg, gamma_sl, gamma_lg):
+    return lib().ora_young_angle(float(gamma_sg), float(gamma_sl), float(gamma_lg))
+
+
+def huang_angle(params, rho_in, rho_out):
+    op = make_params(params)
+    return lib().ora_huang_angle(ctypes.byref(op), float(rho_in), float(rho_out))
 
 
 def to_gpu_layout(state):

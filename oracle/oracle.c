@@ -840,3 +840,25 @@ void ora_adjoint_step(const ora_lattice* Lc, const double* state_t, double* lam,
       }
   free(dn); free(drho); free(dj); free(dpsi); free(dF); free(du);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Eq. (young): cos(theta) = (gamma_SG - gamma_SL) / gamma_LG, the droplet
+ * species being the liquid.  Returns theta in degrees, clamped to [0, 180]
+ * when |cos| > 1 (complete wetting or drying).                             */
+double ora_young_angle(double gamma_sg, double gamma_sl, double gamma_lg) {
+  double c = (gamma_sg - gamma_sl) / gamma_lg;
+  if (c > 1.0) c = 1.0;
+  if (c < -1.0) c = -1.0;
+  return acos(c) * RAD2DEG;
+}
+
+/* Eq. (huangSigmaLG), Huang's a-priori estimate for droplet species A:
+ * cos(theta) = (G_ads,B - G_ads,A) / (g_ab (rho_in - rho_out) / 2), with
+ * G_ads,a = g_wall^a psi(rho_wall^b) the adhesion (a repulsion) that species
+ * a feels from the wall, and rho_in, rho_out the A densities of the A-rich
+ * and B-rich bulk phases.  Clamped as above.                               */
+double ora_huang_angle(const ora_params* p, double rho_in, double rho_out) {
+  double gA = p->g_wall[0] * psi_of(p->psi, p->rho_wall[1]);
+  double gB = p->g_wall[1] * psi_of(p->psi, p->rho_wall[0]);
+  return ora_young_angle(gB, gA, p->g_ab * (rho_in - rho_out) / 2.0);
+}

@@ -120,6 +120,14 @@ void ora_pressure_tensor(ora_lattice* L, double* P);
    nodes; profile (nz values) may be NULL. */
 double ora_surface_tension_z(ora_lattice* L, double* profile);
 
+/* Eq. (young) in degrees from the three tensions (liquid = droplet
+   species), clamped to [0, 180]. */
+double ora_young_angle(double gamma_sg, double gamma_sl, double gamma_lg);
+/* Eq. (huangSigmaLG): Huang's estimate for droplet species A from the wall
+   parameters and the A densities of the A-rich (rho_in) and B-rich
+   (rho_out) bulk phases; degrees, clamped. */
+double ora_huang_angle(const ora_params* p, double rho_in, double rho_out);
+
 /* contact angle of the current state; returns 0, or -4 when no droplet */
 int ora_contact_angle(const ora_lattice* L, const ora_ca_cfg* cfg, ora_ca* out);
 /* same, on a given order-parameter field phi (one value per node); solid

@@ -99,3 +99,22 @@ def test_wall_tensions_and_young(ora):
     gA2 = _wall_slab(ora, (0.7, 0.04), W.asymmetric_wall(0.2))
     gB2 = _wall_slab(ora, (0.04, 0.7), W.asymmetric_wall(0.2))
     assert gA2 < gB2
+
+
+def test_young_and_huang_closed_forms(ora):
+    import oracle as O
+    assert O.young_angle(0.03, 0.03, 0.05) == pytest.approx(90.0, abs=1e-12)
+    assert O.young_angle(0.05, 0.02, 0.06) == pytest.approx(60.0, abs=1e-9)
+    assert O.young_angle(0.02, 0.05, 0.06) == pytest.approx(120.0, abs=1e-9)
+    assert O.young_angle(0.2, 0.0, 0.05) == 0.0 and O.young_angle(0.0, 0.2, 0.05) == 180.0
+    # symmetric wall content: 90 degrees for any bulk densities
+    p = W.params(8, 8, 8, 0.12)
+    assert O.huang_angle(p, 0.74, 0.01) == pytest.approx(90.0, abs=1e-12)
+    # wall richer in A by 0.2: cos = g_wall 0.2 / (g (0.74 - 0.01) / 2) with g_wall = g
+    p = W.params(8, 8, 8, 0.12, rho_wall=W.asymmetric_wall(0.2))
+    expect = np.degrees(np.arccos(0.2 / (0.73 / 2.0)))
+    assert O.huang_angle(p, 0.74, 0.01) == pytest.approx(expect, abs=1e-9)
+    # the exponential pseudopotential enters through psi(rho_wall)
+    p = W.params(8, 8, 8, 0.12, rho_wall=(0.7, 0.3), psi=1)
+    c = (np.exp(-0.3) - np.exp(-0.7)) / (0.5 / 2.0)
+    assert O.huang_angle(p, 0.6, 0.1) == pytest.approx(np.degrees(np.arccos(c)), abs=1e-9)
