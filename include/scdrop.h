@@ -177,6 +177,19 @@ scd_status scd_pressure_tensor(scd_lattice* h, double* d_P);
 scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
                                  double* h_profile);
 
+/* Young's equation (Sec. 1, Eq. young) with the droplet species as the
+ * liquid: theta = acos((gamma_SG - gamma_SL) / gamma_LG) in degrees, with
+ * the cosine clamped to [-1, 1] (complete wetting 0, complete drying 180).
+ * Host arithmetic only. */
+double scd_young_angle(double gamma_sg, double gamma_sl, double gamma_lg);
+
+/* Huang's a-priori estimate (Sec. 4.1, Eq. huangSigmaLG) for droplet
+ * species A: cos(theta) = (G_ads,B - G_ads,A) / (g_ab (rho_in - rho_out) / 2)
+ * with G_ads,a = g_wall^a psi(rho_wall^b), the repulsion species a feels from
+ * the wall, and rho_in, rho_out the A densities of the A-rich and B-rich
+ * bulk phases; degrees, clamped as above.  NaN if p is NULL. */
+double scd_huang_angle(const scd_params* p, double rho_in, double rho_out);
+
 /* Mass per species, total momentum and the all-finite flag, accumulated in
  * FP64 with a fixed reduction order (bit-reproducible).  Synchronises.
  * Returns SCD_ENONFINITE (with *out filled) if any population is not finite. */

@@ -73,6 +73,8 @@ _PROTOS = {
     "scd_fill_state": [_VP, _D],
     "scd_density": [_VP, _VP],
     "scd_pressure_tensor": [_VP, _VP],
+    "scd_young_angle": [_D, _D, _D],
+    "scd_huang_angle": [ctypes.POINTER(ScdParams), _D, _D],
     "scd_surface_tension_z": [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "scd_observables": [_VP, ctypes.POINTER(ScdObs)],
     "scd_contact_angle": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
@@ -106,7 +108,7 @@ _PROTOS = {
 def header_symbols():
     """Names of the functions that include/scdrop.h declares."""
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:scd_status|int64_t|const char\*)\s+(scd_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:scd_status|int64_t|double|const char\*)\s+(scd_\w+)\(", text, re.M)))
 
 
 def lib():
@@ -123,6 +125,8 @@ def lib():
         L.scd_step_count.restype = _I64
         L.scd_last_error.restype = ctypes.c_char_p
         L.scd_version.restype = ctypes.c_char_p
+        L.scd_young_angle.restype = _D
+        L.scd_huang_angle.restype = _D
         _lib = L
     return _lib
 
@@ -359,6 +363,17 @@ class Lattice:
 
     def graph_replay(self, reps=1):
         check(lib().scd_graph_replay(self.h, int(reps)))
+
+
+def young_angle(gamma_sg, gamma_sl, gamma_lg):
+    """Eq. young in degrees (liquid = droplet species), clamped."""
+    return lib().scd_young_angle(float(gamma_sg), float(gamma_sl), float(gamma_lg))
+
+
+def huang_angle(params, rho_in, rho_out):
+    """Huang's estimate (Eq. huangSigmaLG) for droplet species A, degrees."""
+    sp = make_params(params)
+    return lib().scd_huang_angle(ctypes.byref(sp), float(rho_in), float(rho_out))
 
 
 def tile_list():

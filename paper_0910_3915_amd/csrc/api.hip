@@ -365,6 +365,19 @@ scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
   return SCD_OK;
 }
 
+double scd_young_angle(double gamma_sg, double gamma_sl, double gamma_lg) {
+  const double c = std::min(1.0, std::max(-1.0, (gamma_sg - gamma_sl) / gamma_lg));
+  return std::acos(c) * (180.0 / M_PI);
+}
+
+double scd_huang_angle(const scd_params* p, double rho_in, double rho_out) {
+  if (!p) return NAN;
+  auto psi = [&](double r) { return p->psi == SCD_PSI_EXP ? 1.0 - std::exp(-r) : r; };
+  const double ads_a = p->g_wall[0] * psi(p->rho_wall[1]);  // repulsion felt by A
+  const double ads_b = p->g_wall[1] * psi(p->rho_wall[0]);  // ... by B
+  return scd_young_angle(ads_b, ads_a, p->g_ab * (rho_in - rho_out) / 2.0);
+}
+
 scd_status scd_density(scd_lattice* h, double* d_rho) {
   if (!h || !d_rho) return fail(SCD_EINVAL, "NULL argument");
   HIPCHK(launch_density(h->p.dtype, h->pop[h->cur], h->links(), d_rho, (int)h->N, h->stream));

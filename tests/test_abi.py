@@ -71,3 +71,17 @@ def test_batch_sizes_reject_mixed_dtypes():
                            B.make_params(W.params(16, 16, 16, 0.1, dtype="f32")))
     n = ctypes.c_size_t()
     assert scd.lib().scd_batch_sizes(2, ps, ctypes.byref(n)) == B.SCD_EINVAL
+
+
+def test_host_angle_formulas_match_oracle():
+    """Young's equation and Huang's estimate are host arithmetic in the
+    library; they must agree with the oracle's for both pseudopotentials."""
+    import oracle as O
+    import workloads as W
+    for t in ((0.03, 0.03, 0.05), (0.05, 0.02, 0.06), (0.02, 0.05, 0.06), (0.3, 0.0, 0.05)):
+        assert scd.binding.young_angle(*t) == pytest.approx(O.young_angle(*t), abs=1e-12)
+    for psi in (0, 1):
+        for d in (-0.4, -0.1, 0.0, 0.3):
+            p = W.params(8, 8, 8, 0.12, rho_wall=W.asymmetric_wall(d), psi=psi)
+            assert scd.binding.huang_angle(p, 0.74, 0.01) == pytest.approx(
+                O.huang_angle(p, 0.74, 0.01), abs=1e-12)
