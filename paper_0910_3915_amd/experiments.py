@@ -1,10 +1,12 @@
 """Workload drivers on top of the library: the wall-asymmetry sweep, the
-gradient fit of the wall parameters to a target angle, and the structured-
-surface (posts) run.  Each prints JSON lines and returns a dict.
+gradient fit of the wall parameters to a target angle, the structured-
+surface (posts) run, and the planar surface-tension route to the contact
+angle with Huang's estimate.  Each prints JSON lines and returns a dict.
 
     python -m paper_0910_3915_amd.experiments sweep --dtype f64
     python -m paper_0910_3915_amd.experiments fit --dtype f64
     python -m paper_0910_3915_amd.experiments posts --steps 100000
+    python -m paper_0910_3915_amd.experiments young --dtype f64
 """
 import argparse
 import json
@@ -133,6 +135,116 @@ def fit(dtype="f64", iters=50, steps=2000, ckpt=100, target=120.0, max_step=0.05
     return {"history": hist, "final": res}
 
 
+def _planar_batch(cases, steps, stream, checkpoints=(0.5, 1.0)):
+    """Relax planar systems together in one batched launch; returns, for
+    each checkpoint fraction, the surface-tension sums and the views."""
+    B_ = B.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=stream)
+    for i, c in enumerate(cases):
+        B_.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    B_.autotune(2, None)  # advances the members: start again afterwards
+    for i, c in enumerate(cases):
+        B_.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    chunk = 1000
+    B_.graph_capture(chunk)
+    done, out = 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for frac in checkpoints:
+        target = int(round(frac * steps))
+        while done + chunk <= target:
+            B_.graph_replay(1)
+            done += chunk
+        if target > done:
+            B_.step(target - done)
+            done = target
+            B_.graph_capture(chunk)
+        torch.cuda.synchronize()
+        out.append((done, [B_.view(i).surface_tension_z()[0] for i in range(len(cases))]))
+    sec = time.perf_counter() - t0
+    return B_, out, sec
+
+
+def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
+    """Contact angles from planar surface tensions (Sec. 4.1, Eq. gammaMechDef
+    and Eq. young) and Huang's estimate (Eq. huangSigmaLG), against the
+    geometric angle.
+
+    Part 1, g = 0.12 and the nine wall asymmetries of the droplet sweep:
+    the A-B lamella and, per asymmetry, the A-wall and B-wall slabs
+    (32 x 8 x 128, periodic), relaxed together in one batch; Young's angle
+    cos = (gamma_Bw - gamma_Aw) / gamma_AB; Huang's estimate from the bulk A
+    densities of the relaxed lamella; the geometric E1/E2 angles of the
+    128 x 128 x 64 droplets after 20000 steps.
+    Part 2, the paper's grid: g = 0.00 .. 0.20 (step 0.02) against the wall
+    density eta = 0.00 .. 0.60 (step 0.02) with wall content (0, eta), all
+    693 planar systems in one batch.  Young's angle where an A-B interface
+    exists (gamma_AB > 1e-6)."""
+    stream = torch.cuda.Stream()
+    res = {}
+    # ---- part 1
+    deltas = [float(d) for d in W.THROUGHPUT_DELTAS]
+    g = 0.12
+    cases = [W.planar_case("AB", g, dtype=dtype)]
+    for d in deltas:
+        wall = W.asymmetric_wall(d)
+        cases += [W.planar_case("Aw", g, wall, dtype=dtype), W.planar_case("Bw", g, wall, dtype=dtype)]
+    Bt, snaps, sec = _planar_batch(cases, steps, stream)
+    nodes = sum(fluid_nodes(c["solid"]) for c in cases)
+    (s_half, gam_half), (s_end, gam) = snaps
+    dens = Bt.view(0).density().cpu().numpy()  # (2, nz, ny, nx)
+    nz = cases[0]["params"]["nz"]
+    rho_in, rho_out = float(dens[0, nz // 2].mean()), float(dens[0, 0].mean())
+    g_ab = gam[0] / 2.0
+    emit({"exp": "young_planar", "dtype": dtype, "steps": s_end, "gamma_AB": g_ab,
+          "gamma_AB_half": gam_half[0] / 2.0, "rho_in": rho_in, "rho_out": rho_out,
+          "members": len(cases), "mlups": nodes * s_end / sec / 1e6})
+    del Bt
+    geo = {}
+    if with_droplets:
+        for r in sweep(dtype, 20000, "full", deltas)["sweep"]:
+            geo[r["delta"]] = r
+    rows = []
+    for j, d in enumerate(deltas):
+        gAw, gBw = gam[1 + 2 * j] / 2.0, gam[2 + 2 * j] / 2.0
+        p = W.params(8, 8, 8, g, rho_wall=W.asymmetric_wall(d))
+        row = {"exp": "young", "delta": d, "gamma_Aw": gAw, "gamma_Bw": gBw, "gamma_AB": g_ab,
+               "gamma_Aw_half": gam_half[1 + 2 * j] / 2.0, "gamma_Bw_half": gam_half[2 + 2 * j] / 2.0,
+               "theta_young": B.young_angle(gBw, gAw, g_ab),
+               "theta_huang": B.huang_angle(p, rho_in, rho_out)}
+        if d in geo:
+            row["theta_e1"] = geo[d]["theta_e1"]
+            row["theta_e2"] = geo[d]["theta_e2"]
+        rows.append(emit(row))
+    res["g012"] = rows
+    # ---- part 2
+    gs = [round(0.02 * i, 2) for i in range(11)]
+    etas = [round(0.02 * i, 2) for i in range(31)]
+    cases, index = [], {}
+    for gg in gs:
+        index[(gg, "AB")] = len(cases)
+        cases.append(W.planar_case("AB", gg, dtype=dtype))
+        for eta in etas:
+            for kind in ("Aw", "Bw"):
+                index[(gg, eta, kind)] = len(cases)
+                cases.append(W.planar_case(kind, gg, (0.0, eta), dtype=dtype))
+    Bt, snaps, sec = _planar_batch(cases, grid_steps, stream, checkpoints=(1.0,))
+    nodes = sum(fluid_nodes(c["solid"]) for c in cases)
+    _, gam = snaps[0]
+    del Bt
+    table = []
+    for gg in gs:
+        gab = gam[index[(gg, "AB")]] / 2.0
+        line = []
+        for eta in etas:
+            gAw, gBw = gam[index[(gg, eta, "Aw")]] / 2.0, gam[index[(gg, eta, "Bw")]] / 2.0
+            line.append(B.young_angle(gBw, gAw, gab) if gab > 1e-6 else None)
+        table.append(emit({"exp": "young_grid", "g": gg, "gamma_AB": gab, "eta": etas, "theta_young": line}))
+    res["grid"] = table
+    res["grid_perf"] = emit({"exp": "young_grid_perf", "members": len(cases), "steps": grid_steps,
+                             "seconds": sec, "mlups": nodes * grid_steps / sec / 1e6})
+    return res
+
+
 def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000):
     """Droplet on a square array of posts (width 6, pitch 12, height 12) in
     a 384 x 384 x 192 box, wall asymmetry -0.3; then one adjoint pass over
@@ -175,7 +287,7 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "fit", "posts"])
+    ap.add_argument("what", choices=["sweep", "fit", "posts", "young"])
     ap.add_argument("--dtype", default=None, help="f64 or f32 (posts default f32, others f64)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--box", default="full")
@@ -186,6 +298,8 @@ def main():
         sweep(a.dtype or "f64", a.steps or 20000, a.box)
     elif a.what == "fit":
         fit(a.dtype or "f64", a.iters, a.steps or 2000)
+    elif a.what == "young":
+        young(a.dtype or "f64", a.steps or 20000)
     else:
         posts(a.steps or 100000, a.adjoint_steps, a.dtype or "f32")
 

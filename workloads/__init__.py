@@ -154,6 +154,30 @@ def config_posts(seed=0, dtype="f32"):
             "ca": ca_cfg(nx, ny, z_solid_top=12, offset=5)}
 
 
+def planar_case(kind, g_ab, rho_wall=(0.5, 0.5), nx=32, ny=8, nz=128, dtype="f64",
+                rho_in=0.7, rho_out=0.04):
+    """Planar systems of the surface-tension measurement, periodic on all
+    axes, interfaces normal to z:
+      "AB": an A lamella on z in [nz/4, 3nz/4) in B (two A-B interfaces);
+      "Aw"/"Bw": solid on z < nz/2, the upper half filled with the A-rich
+      (B-rich) phase (two fluid-wall interfaces).
+    The A-rich phase holds (rho_in, rho_out), the B-rich phase the reverse;
+    g_wall = g_ab."""
+    z = np.arange(nz)[:, None, None] * np.ones((1, ny, nx))
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    if kind == "AB":
+        a_rich = (z >= nz // 4) & (z < 3 * nz // 4)
+    else:
+        solid[: nz // 2] = 1
+        a_rich = np.full(z.shape, kind == "Aw")
+    ra = np.where(a_rich, rho_in, rho_out).astype(np.float64)
+    rb = np.where(a_rich, rho_out, rho_in).astype(np.float64)
+    ra[solid == 1] = 0.0
+    rb[solid == 1] = 0.0
+    p = params(nx, ny, nz, g_ab, rho_wall=tuple(rho_wall), dtype=dtype)
+    return {"params": p, "solid": solid, "rho_a": ra, "rho_b": rb, "kind": kind}
+
+
 def batch_draw(n=64, seed=0):
     """Box sizes and parameters of the batched sweep: Lx, Ly uniform in
     {64..128}, Lz in {48..96}, all multiples of 8; g_ab uniform in
