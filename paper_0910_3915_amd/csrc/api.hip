@@ -141,12 +141,12 @@ struct scd_lattice {
 
 namespace {
 
-// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet): both
-// precisions run best as the species-split z-march that issues all loads of
-// a plane at once, FP64 on 32 x 4 tiles with one wave per SIMD (its register
-// set does not fit two), FP32 on 32 x 8 tiles.
+// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet), both on
+// 32 x 8 tiles at two waves per SIMD: FP64 as the species-split z-march with
+// streaming stores, FP32 as the variant that issues all loads of a plane at
+// once (in FP64 that one needs 265 registers and falls to one wave).
 int default_variant(int dtype) {
-  int v = dtype == SCD_F64 ? variant_find(32, 4, 5, 1) : variant_find(32, 8, 5, 2);
+  int v = dtype == SCD_F64 ? variant_find(32, 8, 3, 2) : variant_find(32, 8, 5, 2);
   return v < 0 ? 0 : v;
 }
 

@@ -343,7 +343,7 @@ struct SplitTile {
 
 template <typename real, int TX, int TY, bool NT_STORE, bool JOINT>
 __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, int by, int za,
-                                                int zb, real* __restrict__ lds) {
+                                                int zb, real* __restrict__ lds, int dir = 1) {
   auto store = [](char* base, uint32_t off, real v) {
     if constexpr (NT_STORE) st_off_nt<real>(base, off, v);
     else st_off<real>(base, off, v);
@@ -399,7 +399,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
     for (int h = 0; h < T::HPT; ++h)
       lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
   };
-  load_links(za - 1, lbi, lbh);
+  load_links(dir > 0 ? za - 1 : zb, lbi, lbh);
 
   // Parameters of the e values, held in registers for the whole march.
   const real gab = L.ph.gab;
@@ -412,8 +412,8 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
 
   // The halo of plane zr is pulled and reduced first, then the interior
   // (a fence between them bounds the live registers: the interior set is
-  // pulled while the collided plane's set is still held); the masks of
-  // plane zr + 1 are requested behind the interior loads.
+  // pulled while the collided plane's set is still held); the masks of the
+  // next plane of the march are requested behind the interior loads.
   auto plane_fenced = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
@@ -439,7 +439,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
       if (keep) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, nout);
       else pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, m);
     }
-    load_links(zr + 1, lbi, lbh);
+    load_links(zr + dir, lbi, lbh);
     real r = 0;
     if (!solid_out) {
       if (keep) {
@@ -454,7 +454,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   };
 
   // All loads of plane zr are issued before any is used: the interior set,
-  // then the halo, then the masks of plane zr + 1.
+  // then the halo, then the masks of the next plane of the march.
   auto plane_joint = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
@@ -473,7 +473,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
         pull19(L.src, N, hsp[h], ih, hx[h], hy[h], zs, nx, ny, lbh[h], hm[h]);
     }
     uint32_t nli, nlh[T::HPT];
-    load_links(zr + 1, nli, nlh);
+    load_links(zr + dir, nli, nlh);
     real r = 0;
     if (!solid_out) {
       if (keep) {
@@ -506,13 +506,16 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
     else plane_fenced(zr, keep, nout, solid_out);
   };
 
+  // March up (dir = 1) from za - 1 or down (dir = -1) from zb; the planes
+  // of [za, zb) are collided, each once all three of its e planes are in.
   const Phys<real>& ph = L.ph;
-  plane(za - 1, false, nnext, solid_next);
-  plane(za, true, ncur, solid_cur);
-  for (int p = za + 1; p <= zb; ++p) {
-    plane(p, p < zb, nnext, solid_next);
+  const int first = dir > 0 ? za - 1 : zb, last = dir > 0 ? zb : za - 1;
+  plane(first, false, nnext, solid_next);
+  plane(first + dir, true, ncur, solid_cur);
+  for (int p = first + 2 * dir; dir > 0 ? p <= last : p >= last; p += dir) {
+    plane(p, dir > 0 ? p < zb : p >= za, nnext, solid_next);
     __syncthreads();
-    const int zc = p - 1;
+    const int zc = p - dir;
     // every lane takes part in the swap; inactive and wall lanes carry zeros
     real rho, jx, jy, jz;
     moments(ncur, rho, jx, jy, jz);
@@ -734,18 +737,19 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
 
 // Map the hardware block id to a tile.  Workgroups are handed to the 8 XCDs
 // round-robin; with remap each XCD receives one contiguous range of tiles
-// (x fastest, then y, then z-chunk), so neighbouring tiles that share halo
-// lines and chunk-boundary planes share that XCD's L2.
-__device__ __forceinline__ bool tile_of_block(int b, int total, int remap, int gx, int gy, int& bx,
+// (z-chunk fastest, then x, then y), so the chunks of a column, which share
+// their boundary planes, and neighbouring columns, which share halo lines,
+// sit in one XCD's L2.
+__device__ __forceinline__ bool tile_of_block(int b, int total, int remap, int gx, int gz, int& bx,
                                               int& by, int& bz) {
   if (remap) {
     int per = (total + 7) / 8;
     b = (b & 7) * per + (b >> 3);
     if (b >= total) return false;
   }
-  bx = b % gx;
-  by = (b / gx) % gy;
-  bz = b / (gx * gy);
+  bz = b % gz;
+  bx = (b / gz) % gx;
+  by = b / (gz * gx);
   return true;
 }
 
@@ -765,13 +769,13 @@ struct StepShape {
 
 template <typename real, int TX, int TY, int VAR>
 __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, int za, int zb,
-                                         real* lds) {
+                                         real* lds, int dir = 1) {
   if constexpr (VAR == VAR_SPLIT)
-    step_tile_split<real, TX, TY, false, false>(L, bx, by, za, zb, lds);
+    step_tile_split<real, TX, TY, false, false>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_SPLIT_NT)
-    step_tile_split<real, TX, TY, true, false>(L, bx, by, za, zb, lds);
+    step_tile_split<real, TX, TY, true, false>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_JOINT)
-    step_tile_split<real, TX, TY, true, true>(L, bx, by, za, zb, lds);
+    step_tile_split<real, TX, TY, true, true>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -784,10 +788,14 @@ __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_step(LatDev<real> L, int gx, int gy, int nchunks, int zc, int remap) {
   __shared__ __align__(16) real lds[StepShape<real, TX, TY, VAR>::LDS_REALS];
   int bx, by, bz;
-  if (!tile_of_block(blockIdx.x, gx * gy * nchunks, remap, gx, gy, bx, by, bz)) return;
+  if (!tile_of_block(blockIdx.x, gx * gy * nchunks, remap, gx, nchunks, bx, by, bz)) return;
   const int za = bz * zc;
   const int zb = min(za + zc, L.nz);
-  run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds);
+  // even chunks march down, odd ones up: two neighbouring chunks (adjacent
+  // workgroups, one XCD) reach their shared boundary planes at the same time
+  // -- both at the start or both at the end -- so one pull of those planes
+  // from HBM serves both through L2
+  run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds, (bz & 1) || nchunks == 1 ? 1 : -1);
 }
 
 // Batched: a persistent grid walks a list of (lattice, tile) items.
