@@ -245,6 +245,50 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
     return res
 
 
+def sizes(dtype="f32", etas=(0.1, 0.2, 0.3, 0.35), boxes=((128, 40000), (256, 80000)), g=0.16,
+          report_every=10000, stream=None):
+    """The paper's size/wettability study (Sec. 4): droplets of initial volume
+    (L * 70 / 128)^3 -- 70^3 in the 128^3 box, 140^3 in 256^3 -- started as
+    hemispheres of A (0.7 / 0.04, noise 1e-3, seed 0) on one solid layer at
+    z = 0 (periodic in z, so that layer is also the ceiling), the paper's
+    pseudopotential psi = 1 - exp(-rho), g = 0.16 and the paper's single wall
+    parameter: wall content (0, eta), g_wall = g.  Reports theta_E1/E2 every
+    report_every steps and, per eta, the relative change from the small to
+    the large box."""
+    stream = stream or torch.cuda.Stream()
+    out = {}
+    for L_, steps in boxes:
+        vol = (70.0 * L_ / 128.0) ** 3
+        radius = (3.0 * vol / (2.0 * np.pi)) ** (1.0 / 3.0)
+        solid = W.walls_mask(L_, L_, L_, floor=True, ceiling=False)
+        nf = fluid_nodes(solid)
+        for eta in etas:
+            p = W.params(L_, L_, L_, g, rho_wall=(0.0, eta), psi=1, dtype=dtype)
+            ra, rb = W.cap_densities(L_, L_, L_, radius, 0.5, solid)
+            lat = B.Lattice(p, solid, stream=stream)
+            lat.init_equilibrium(ra, rb)
+            cfg = W.ca_cfg(L_, L_)
+            done, sec = 0, 0.0
+            while done < steps:
+                n = min(report_every, steps - done)
+                sec += timed_steps(lat, n, stream)
+                done += n
+                ca = lat.contact_angle(cfg)
+                rec = emit({"exp": "sizes", "box": L_, "eta": eta, "step": done, "radius0": radius,
+                            "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
+                            "mlups": nf * done / sec / 1e6})
+            out[(L_, eta)] = rec
+            del lat
+            torch.cuda.empty_cache()
+    small, large = boxes[0][0], boxes[-1][0]
+    for eta in etas:
+        if (small, eta) in out and (large, eta) in out:
+            a, b = out[(small, eta)]["theta_e1"], out[(large, eta)]["theta_e1"]
+            emit({"exp": "sizes_change", "eta": eta, "theta_small": a, "theta_large": b,
+                  "relative_change_pct": 100.0 * (b - a) / a})
+    return out
+
+
 def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000):
     """Droplet on a square array of posts (width 6, pitch 12, height 12) in
     a 384 x 384 x 192 box, wall asymmetry -0.3; then one adjoint pass over
@@ -287,17 +331,25 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "fit", "posts", "young"])
+    ap.add_argument("what", choices=["sweep", "fit", "posts", "young", "sizes"])
+    ap.add_argument("--box", type=int, default=None, help="sizes: run one box edge only")
     ap.add_argument("--dtype", default=None, help="f64 or f32 (posts default f32, others f64)")
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--box", default="full")
+    ap.add_argument("--sweep-box", default="full")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     a = ap.parse_args()
     if a.what == "sweep":
-        sweep(a.dtype or "f64", a.steps or 20000, a.box)
+        sweep(a.dtype or "f64", a.steps or 20000, a.sweep_box)
     elif a.what == "fit":
         fit(a.dtype or "f64", a.iters, a.steps or 2000)
+    elif a.what == "sizes":
+        boxes = ((128, 40000), (256, 80000))
+        if a.box:
+            boxes = tuple(b for b in boxes if b[0] == a.box)
+        if a.steps:
+            boxes = tuple((b[0], a.steps) for b in boxes)
+        sizes(a.dtype or "f32", boxes=boxes)
     elif a.what == "young":
         young(a.dtype or "f64", a.steps or 20000)
     else:
