@@ -842,6 +842,85 @@ void ora_adjoint_step(const ora_lattice* Lc, const double* state_t, double* lam,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Eq. (mechRadGamma): gamma = int_0^rmax (r / R_s)^2 (P_N - P_T) dr about a
+ * centre c (Sec. 4.1).  The integral is a sum over shells of unit width:
+ * shell b holds the fluid nodes with b <= |x - c| < b + 1 (minimum-image
+ * distances on the periodic axes), at radius r_b = b + 1/2.  P_N = d.P.d / |d|^2
+ * and P_T = (tr P - P_N) / 2 with d = x - c; the node at the centre itself
+ * adds 0.  profile[b] is the shell mean of P_N - P_T, phi_profile[b] that of
+ * phi = rho_A - rho_B.  R_s is the first outward crossing of the shell means
+ * of phi from > 0 to <= 0, linearly interpolated between shell radii; the
+ * sum runs over the shells with r_b <= rmax.  Returns gamma, or NaN (and
+ * R_s = NaN) when phi has no such crossing.                                */
+static double min_image(double d, int n) {
+  if (d >= 0.5 * n) d -= n;
+  if (d < -0.5 * n) d += n;
+  return d;
+}
+
+double ora_radial_tension(ora_lattice* L, const double* center, double rmax, int nbins,
+                          double* profile, double* phi_profile, double* Rs) {
+  double* P = (double*)malloc(L->N * 6 * sizeof(double));
+  double* rho = (double*)malloc(L->N * 2 * sizeof(double));
+  double* sv = (double*)calloc((size_t)nbins, sizeof(double));
+  double* sp = (double*)calloc((size_t)nbins, sizeof(double));
+  double* cnt = (double*)calloc((size_t)nbins, sizeof(double));
+  ora_pressure_tensor(L, P);
+  ora_density(L, rho);
+  for (int z = 0; z < L->nz; ++z)
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) {
+        size_t i = node_at(L, x, y, z);
+        if (L->solid[i]) continue;
+        double d[3] = {min_image(x - center[0], L->nx), min_image(y - center[1], L->ny),
+                       min_image(z - center[2], L->nz)};
+        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        int b = (int)floor(sqrt(r2));
+        while ((double)(b + 1) * (b + 1) <= r2) ++b;
+        while (b > 0 && (double)b * b > r2) --b;
+        if (b >= nbins) continue;
+        const double* p = P + i * 6;
+        double v = 0.0;
+        if (r2 > 0.0) {
+          double pn = (d[0] * d[0] * p[0] + d[1] * d[1] * p[1] + d[2] * d[2] * p[2] +
+                       2.0 * (d[0] * d[1] * p[3] + d[0] * d[2] * p[4] + d[1] * d[2] * p[5])) / r2;
+          double pt = 0.5 * (p[0] + p[1] + p[2] - pn);
+          v = pn - pt;
+        }
+        sv[b] += v;
+        sp[b] += rho[i * 2] - rho[i * 2 + 1];
+        cnt[b] += 1.0;
+      }
+  for (int b = 0; b < nbins; ++b) {
+    sv[b] = cnt[b] > 0 ? sv[b] / cnt[b] : 0.0;
+    sp[b] = cnt[b] > 0 ? sp[b] / cnt[b] : 0.0;
+    if (profile) profile[b] = sv[b];
+    if (phi_profile) phi_profile[b] = sp[b];
+  }
+  double R = NAN;
+  for (int b = 0; b + 1 < nbins; ++b)
+    if (sp[b] > 0.0 && sp[b + 1] <= 0.0) {
+      R = (b + 0.5) + sp[b] / (sp[b] - sp[b + 1]);
+      break;
+    }
+  double g = NAN;
+  if (!isnan(R)) {
+    g = 0.0;
+    for (int b = 0; b < nbins && b + 0.5 <= rmax; ++b) {
+      double rb = b + 0.5;
+      g += (rb / R) * (rb / R) * sv[b];
+    }
+  }
+  *Rs = R;
+  free(P);
+  free(rho);
+  free(sv);
+  free(sp);
+  free(cnt);
+  return g;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Eq. (young): cos(theta) = (gamma_SG - gamma_SL) / gamma_LG, the droplet
  * species being the liquid.  Returns theta in degrees, clamped to [0, 180]
  * when |cos| > 1 (complete wetting or drying).                             */

@@ -120,6 +120,14 @@ void ora_pressure_tensor(ora_lattice* L, double* P);
    nodes; profile (nz values) may be NULL. */
 double ora_surface_tension_z(ora_lattice* L, double* profile);
 
+/* Eq. (mechRadGamma) about centre[3]: shells of unit width (bin b holds
+   b <= |x - c| < b + 1, minimum image), profile[b] / phi_profile[b] (nbins
+   each, may be NULL) the shell means of P_N - P_T and of phi, *Rs the
+   outward phi crossing; returns the sum over shells with b + 1/2 <= rmax of
+   ((b + 1/2) / R_s)^2 profile[b], or NaN without a crossing. */
+double ora_radial_tension(ora_lattice* L, const double* center, double rmax, int nbins,
+                          double* profile, double* phi_profile, double* Rs);
+
 /* Eq. (young) in degrees from the three tensions (liquid = droplet
    species), clamped to [0, 180]. */
 double ora_young_angle(double gamma_sg, double gamma_sl, double gamma_lg);

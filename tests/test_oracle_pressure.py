@@ -118,3 +118,37 @@ def test_young_and_huang_closed_forms(ora):
     p = W.params(8, 8, 8, 0.12, rho_wall=(0.7, 0.3), psi=1)
     c = (np.exp(-0.3) - np.exp(-0.7)) / (0.5 / 2.0)
     assert O.huang_angle(p, 0.6, 0.1) == pytest.approx(np.degrees(np.arccos(c)), abs=1e-9)
+
+
+def test_radial_tension_uniform_state(ora):
+    n = 12
+    L = ora.Lattice(W.params(n, n, n, 0.1))
+    L.init_equilibrium(np.full((n, n, n), 0.5), np.full((n, n, n), 0.3))
+    g, rs, prof, pphi = L.radial_tension([6.0, 6.0, 6.0], 5.0, 6)
+    assert np.isnan(g) and np.isnan(rs)
+    assert np.allclose(prof, 0.0, atol=1e-14) and np.allclose(pphi, 0.2, atol=1e-14)
+
+
+@pytest.mark.slow
+def test_radial_tension_free_droplet(ora):
+    """A relaxed free droplet: the radial mechanical-equilibrium identity
+    p_in - p_out = 2 int (P_N - P_T) / r dr holds within 10 %, R_s is the
+    radius of the droplet's volume within 0.2, and Eq. mechRadGamma agrees
+    with the Laplace tension dp R_s / 2 within 10 %."""
+    n, g = 48, 0.1
+    L = ora.Lattice(W.params(n, n, n, g))
+    ra, rb = W.sphere_densities(n, 8.0)
+    L.init_equilibrium(ra, rb)
+    L.step(3000)
+    rmax = n / 2 - 5
+    gam, rs, prof, pphi = L.radial_tension([n / 2] * 3, rmax, n // 2)
+    r = L.density()
+    p = (r[..., 0] + r[..., 1]) / 3.0 + 10.0 * g * r[..., 0] * r[..., 1]
+    c = n // 2
+    dp = p[c - 1:c + 2, c - 1:c + 2, c - 1:c + 2].mean() - p[0:2, 0:2, 0:2].mean()
+    rb_ = np.arange(n // 2) + 0.5
+    ident = (2.0 * prof / rb_)[rb_ <= rmax].sum()
+    assert abs(ident - dp) < 0.10 * dp
+    volume = np.count_nonzero(r[..., 0] > r[..., 1])
+    assert abs(rs - (3.0 * volume / (4.0 * np.pi)) ** (1.0 / 3.0)) < 0.2
+    assert abs(gam - dp * rs / 2.0) < 0.10 * dp * rs / 2.0
