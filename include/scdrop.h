@@ -177,6 +177,22 @@ scd_status scd_pressure_tensor(scd_lattice* h, double* d_P);
 scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
                                  double* h_profile);
 
+/* Radial surface tension of Eq. (mechRadGamma) about h_center (3 host
+ * doubles, lattice coordinates): shells of unit width, shell b holding the
+ * fluid nodes with b <= |x - c| < b + 1 (minimum image on the periodic
+ * axes, decided by exact comparisons on |x - c|^2), radius r_b = b + 1/2.
+ * Per node P_N = d.P.d / |d|^2 and P_T = (tr P - P_N) / 2 with d = x - c
+ * (the centre node adds 0).  h_profile / h_phi_profile (nbins host doubles
+ * each, or NULL): shell means of P_N - P_T and of phi.  *h_Rs: first
+ * outward crossing of the shell means of phi from > 0 to <= 0, linearly
+ * interpolated; *h_gamma = sum over shells with r_b <= rmax of
+ * (r_b / R_s)^2 profile[b].  d_P: scratch of 6 N doubles.  nbins in
+ * [2, 1365].  Returns SCD_ENOINTERFACE (gamma, R_s NaN) without a
+ * crossing.  Synchronises. */
+scd_status scd_radial_tension(scd_lattice* h, double* d_P, const double* h_center, double rmax,
+                              int32_t nbins, double* h_profile, double* h_phi_profile,
+                              double* h_Rs, double* h_gamma);
+
 /* Young's equation (Sec. 1, Eq. young) with the droplet species as the
  * liquid: theta = acos((gamma_SG - gamma_SL) / gamma_LG) in degrees, with
  * the cosine clamped to [-1, 1] (complete wetting 0, complete drying 180).

@@ -365,6 +365,48 @@ scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
   return SCD_OK;
 }
 
+scd_status scd_radial_tension(scd_lattice* h, double* d_P, const double* h_center, double rmax,
+                              int32_t nbins, double* h_profile, double* h_phi_profile,
+                              double* h_Rs, double* h_gamma) {
+  if (!h || !d_P || !h_center || !h_Rs || !h_gamma) return fail(SCD_EINVAL, "NULL argument");
+  const int maxb = RED_BLOCKS * RED_STRIDE / 3;
+  if (nbins < 2 || nbins > maxb) return fail(SCD_EINVAL, "nbins must be in [2, %d]", maxb);
+  scd_status st = scd_pressure_tensor(h, d_P);
+  if (st) return st;
+  double* shells = (double*)h->wd(h->wl.partials);
+  HIPCHK(launch_radial(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
+                       h_center, nbins, d_P, shells, h->stream));
+  std::vector<double> sh(3 * (size_t)nbins);
+  HIPCHK(hipMemcpyAsync(sh.data(), shells, sh.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<double> prof(nbins), phi(nbins);
+  for (int b = 0; b < nbins; ++b) {
+    const double n = sh[3 * b + 2];
+    prof[b] = n > 0 ? sh[3 * b] / n : 0.0;
+    phi[b] = n > 0 ? sh[3 * b + 1] / n : 0.0;
+  }
+  if (h_profile) std::copy(prof.begin(), prof.end(), h_profile);
+  if (h_phi_profile) std::copy(phi.begin(), phi.end(), h_phi_profile);
+  double R = NAN;
+  for (int b = 0; b + 1 < nbins; ++b)
+    if (phi[b] > 0.0 && phi[b + 1] <= 0.0) {
+      R = (b + 0.5) + phi[b] / (phi[b] - phi[b + 1]);
+      break;
+    }
+  *h_Rs = R;
+  if (std::isnan(R)) {
+    *h_gamma = NAN;
+    return fail(SCD_ENOINTERFACE, "phi has no outward crossing about the centre");
+  }
+  double g = 0.0;
+  for (int b = 0; b < nbins && b + 0.5 <= rmax; ++b) {
+    const double rb = b + 0.5;
+    g += (rb / R) * (rb / R) * prof[b];
+  }
+  *h_gamma = g;
+  return SCD_OK;
+}
+
 double scd_young_angle(double gamma_sg, double gamma_sl, double gamma_lg) {
   const double c = std::min(1.0, std::max(-1.0, (gamma_sg - gamma_sl) / gamma_lg));
   return std::acos(c) * (180.0 / M_PI);

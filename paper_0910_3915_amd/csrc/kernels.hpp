@@ -66,6 +66,8 @@ hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* link
                                 hipStream_t s);
 hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
                            int nz, const PhysD& ph, void* rho, double* P, hipStream_t s);
+hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,
+                         const double* c, int nbins, double* P, double* shells, hipStream_t s);
 hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
                                 double* profile, hipStream_t s);
 hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,

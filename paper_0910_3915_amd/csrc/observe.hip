@@ -480,6 +480,91 @@ __global__ __launch_bounds__(256) void k_plane_tension(const uint32_t* __restric
   if (threadIdx.x == 0) profile[z] = v[1] > 0 ? v[0] / v[1] : 0.0;
 }
 
+// Radial decomposition about a centre c (Eq. mechRadGamma): per fluid node,
+// with d = x - c (minimum image on the periodic axes), P_N = d.P.d / |d|^2,
+// P_T = (tr P - P_N) / 2 (the centre node itself adds 0), written over the
+// tensor's first three components: P[i] = P_N - P_T, P[N + i] = phi,
+// P[2N + i] = shell index b (b <= |d| < b + 1, from exact comparisons on
+// |d|^2), or -1 for wall nodes and nodes beyond nbins shells.  Each thread
+// reads all six components of its node before it writes any.
+template <typename real>
+__global__ __launch_bounds__(256) void k_radial_split(const real* __restrict__ pop,
+                                                      const uint32_t* __restrict__ links,
+                                                      int nx, int ny, int nz, double cx,
+                                                      double cy, double cz, int nbins,
+                                                      double* __restrict__ P) {
+  const int N = nx * ny * nz;
+  auto image = [](double d, int n) {
+    if (d >= 0.5 * n) d -= n;
+    if (d < -0.5 * n) d += n;
+    return d;
+  };
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    double v = 0.0, ph = 0.0, bin = -1.0;
+    if (!(links[i] & SELF_SOLID)) {
+      const double d0 = image((i % nx) - cx, nx), d1 = image(((i / nx) % ny) - cy, ny);
+      const double d2 = image((i / (nx * ny)) - cz, nz);
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      int b = (int)floor(sqrt(r2));
+      while ((double)(b + 1) * (b + 1) <= r2) ++b;
+      while (b > 0 && (double)b * b > r2) --b;
+      if (b < nbins) {
+        bin = (double)b;
+        if (r2 > 0.0) {
+          const double p0 = P[i], p1 = P[(size_t)N + i], p2 = P[(size_t)2 * N + i];
+          const double p3 = P[(size_t)3 * N + i], p4 = P[(size_t)4 * N + i];
+          const double p5 = P[(size_t)5 * N + i];
+          const double pn = (d0 * d0 * p0 + d1 * d1 * p1 + d2 * d2 * p2 +
+                             2.0 * (d0 * d1 * p3 + d0 * d2 * p4 + d1 * d2 * p5)) / r2;
+          v = pn - 0.5 * (p0 + p1 + p2 - pn);
+        }
+        double ra = 0, rb = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          ra += (double)pop[(size_t)k * N + i];
+          rb += (double)pop[(size_t)(Q + k) * N + i];
+        }
+        ph = ra - rb;
+      }
+    }
+    P[i] = v;
+    P[(size_t)N + i] = ph;
+    P[(size_t)2 * N + i] = bin;
+  }
+}
+
+// One workgroup per shell b: sums of P_N - P_T and of phi and the node count
+// over the nodes of shell b, in a fixed order -> out[3 b .. 3 b + 2].
+__global__ __launch_bounds__(256) void k_radial_shells(const double* __restrict__ P, int N,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[3 * 16];
+  const double b = (double)blockIdx.x;
+  double v[3] = {0, 0, 0};
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    if (P[(size_t)2 * N + i] != b) continue;
+    v[0] += P[i];
+    v[1] += P[(size_t)N + i];
+    v[2] += 1.0;
+  }
+  block_sum<3>(v, sh);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) out[3 * blockIdx.x + j] = v[j];
+}
+
+hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,
+                         const double* c, int nbins, double* P, double* shells, hipStream_t s) {
+  const size_t N = (size_t)nx * ny * nz;
+  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_radial_split<double>, dim3(blocks), dim3(256), 0, s, (const double*)pop,
+                       links, nx, ny, nz, c[0], c[1], c[2], nbins, P);
+  else
+    hipLaunchKernelGGL(k_radial_split<float>, dim3(blocks), dim3(256), 0, s, (const float*)pop,
+                       links, nx, ny, nz, c[0], c[1], c[2], nbins, P);
+  hipLaunchKernelGGL(k_radial_shells, dim3(nbins), dim3(256), 0, s, P, (int)N, shells);
+  return hipGetLastError();
+}
+
 hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
                            int nz, const PhysD& ph, void* rho, double* P, hipStream_t s) {
   hipError_t e = launch_stream_density(dtype, pop, links, rho, nx, ny, nz, s);

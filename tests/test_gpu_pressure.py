@@ -65,3 +65,45 @@ def test_pressure_and_tension_match_oracle(name, dtype):
     assert np.max(np.abs(P - Po)) <= tol * scale
     assert np.allclose(prof, profo, rtol=0, atol=tol * scale)
     assert abs(gam - go) <= tol * scale * len(prof)
+
+
+def _free_droplet(n=40, r0=8.0, g=0.1):
+    ra, rb = W.sphere_densities(n, r0)
+    return W.params(n, n, n, g), np.zeros((n, n, n), np.uint8), ra, rb
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["free", "sessile", "none"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_radial_tension_matches_oracle(name, dtype):
+    announce(f"radial tension parity: {name} {dtype}")
+    if name == "free":
+        p, solid, ra, rb = _free_droplet()
+        center = [20.0, 20.0, 20.0]
+    elif name == "sessile":
+        p, solid, ra, rb = _droplet()
+        center = [12.0, 10.0, 0.5]
+    else:
+        n = 16
+        p, solid = W.params(n, n, n, 0.1), np.zeros((n, n, n), np.uint8)
+        ra, rb = np.full((n, n, n), 0.5), np.full((n, n, n), 0.3)
+        center = [8.0, 8.0, 8.0]
+    p = dict(p, dtype=dtype)
+    L = scd.Lattice(p, solid)
+    L.init_equilibrium(ra, rb)
+    L.step(300)
+    nb = min(p["nx"], p["ny"], p["nz"]) // 2
+    rmax = nb - 5
+    g, rs, prof, pphi = L.radial_tension(center, rmax, nb)
+    Lo = O.Lattice(dict(p, dtype="f64"), solid)
+    Lo.set_state(gpu_state_as_oracle(L))
+    go, rso, profo, pphio = Lo.radial_tension(center, rmax, nb)
+    if name == "none":
+        assert np.isnan(g) and np.isnan(rs) and np.isnan(go) and np.isnan(rso)
+        return
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    scale = max(np.max(np.abs(profo)), 1e-3)
+    assert np.allclose(prof, profo, rtol=0, atol=tol * scale)
+    assert np.allclose(pphi, pphio, rtol=0, atol=tol)
+    assert abs(rs - rso) < 1e3 * tol
+    assert abs(g - go) <= 1e3 * tol * abs(go)
