@@ -175,6 +175,8 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
     cos = (gamma_Bw - gamma_Aw) / gamma_AB; Huang's estimate from the bulk A
     densities of the relaxed lamella; the geometric E1/E2 angles of the
     128 x 128 x 64 droplets after 20000 steps.
+    The radial tension of a free droplet (64^3, initial radius 16) gives a
+    second Young angle with the same wall tensions.
     Part 2, the paper's grid: g = 0.00 .. 0.20 (step 0.02) against the wall
     density eta = 0.00 .. 0.60 (step 0.02) with wall content (0, eta), all
     693 planar systems in one batch.  Young's angle where an A-B interface
@@ -199,6 +201,15 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
           "gamma_AB_half": gam_half[0] / 2.0, "rho_in": rho_in, "rho_out": rho_out,
           "members": len(cases), "mlups": nodes * s_end / sec / 1e6})
     del Bt
+    # radial tension of a free droplet at the same coupling (Eq. mechRadGamma)
+    n = 64
+    ra, rb = W.sphere_densities(n, 16.0)
+    fd = B.Lattice(W.params(n, n, n, g, dtype=dtype), np.zeros((n, n, n), np.uint8), stream=stream)
+    fd.init_equilibrium(ra, rb)
+    timed_steps(fd, steps, stream)
+    g_rad, rs, _, _ = fd.radial_tension([n / 2.0] * 3, n / 2.0 - 5.0, n // 2)
+    emit({"exp": "young_radial", "dtype": dtype, "steps": steps, "gamma_AB_radial": g_rad, "R_s": rs})
+    del fd
     geo = {}
     if with_droplets:
         for r in sweep(dtype, 20000, "full", deltas)["sweep"]:
@@ -210,6 +221,7 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
         row = {"exp": "young", "delta": d, "gamma_Aw": gAw, "gamma_Bw": gBw, "gamma_AB": g_ab,
                "gamma_Aw_half": gam_half[1 + 2 * j] / 2.0, "gamma_Bw_half": gam_half[2 + 2 * j] / 2.0,
                "theta_young": B.young_angle(gBw, gAw, g_ab),
+               "theta_young_radial": B.young_angle(gBw, gAw, g_rad),
                "theta_huang": B.huang_angle(p, rho_in, rho_out)}
         if d in geo:
             row["theta_e1"] = geo[d]["theta_e1"]
