@@ -163,9 +163,27 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
     g = L.adjoint_read()
     fwd = e[0].elapsed_time(e[1]) / nsteps
     adj = e[2].elapsed_time(e[3]) / nsteps
+    # the whole checkpointed gradient of the gradient workload: 2000 forward
+    # steps with a checkpoint every 100, then the reverse sweep (segment
+    # recompute + adjoint steps)
+    from paper_0910_3915_amd.grad import GradSetup
+    gs = GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], 2000, 100, c["ca"], 120.0,
+                   stream=stream)
+    gs.forward()
+    gs.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs.forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gs.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     return {"workload": "64x64x48 droplet r=14, " + dtype, "forward_ms": round(fwd, 4),
             "adjoint_ms": round(adj, 4), "ratio": round(adj / fwd, 3),
-            "grad_finite": all(x == x for x in g)}
+            "grad_finite": all(x == x for x in g),
+            "checkpointed_2000_steps": {"forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+                                        "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}}
 
 
 def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):

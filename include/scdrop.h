@@ -242,10 +242,12 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
  * (deg).  The parameters are constants of the run; the gradient is taken
  * over these nsteps steps only.
  * Backward (one level): for each segment in reverse, recomputes its states
- * into d_seg (ckpt_every buffers) and applies the adjoint steps; d_lam holds
- * 2 population buffers of scratch.  h_grad[5] = dL/d{rho_wall_A, rho_wall_B,
- * g_ab, g_wall_A, g_wall_B}.  Needs the state left by the forward call; on
- * return the state is the start of the first segment recomputed last.
+ * into d_seg (ckpt_every buffers; each recomputed step writes its slot
+ * directly) and applies the adjoint steps; d_lam holds 2 population buffers
+ * of scratch.  h_grad[5] = dL/d{rho_wall_A, rho_wall_B, g_ab, g_wall_A,
+ * g_wall_B}.  Needs the state left by the forward call; on return the
+ * lattice holds the first checkpoint (the state the forward call started
+ * from).
  * Backward (two levels): inside each level-1 segment, recomputes level-2
  * checkpoints every K2 steps into d_mid (ceil(K1 / K2) buffers) and runs the
  * one-level sweep on each sub-segment with d_seg of K2 buffers: each step is

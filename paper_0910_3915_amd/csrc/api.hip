@@ -552,24 +552,34 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // Reverse sweep over steps [t0, t1) (relative to the checkpointed forward)
 // whose starting state is in d_start: recompute the states into d_seg and
 // run the adjoint steps backwards, lambda ping-ponging in lam[2].
+// Recompute the states t0 .. t1 - 1 of one segment from d_start (the state
+// at t0) and apply the adjoint steps t1 - 1 .. t0.  Each recomputed step
+// writes its successor's slot of d_seg directly (slot j holds state
+// t0 + 1 + j), so the segment costs t1 - t0 - 1 steps and no state copies.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
   const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
-  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_start, bytes, hipMemcpyDeviceToDevice, h->stream));
-  h->step = h->ckpt_base + t0;
-  for (int64_t t = t0; t < t1; ++t) {
-    HIPCHK(hipMemcpyAsync((char*)d_seg + (size_t)(t - t0) * bytes, h->pop[h->cur], bytes,
-                          hipMemcpyDeviceToDevice, h->stream));
-    scd_status st = enqueue_steps(h, 1);
-    if (st) return st;
-  }
+  auto state = [&](int64_t t) -> const void* {
+    return t == t0 ? d_start : (const char*)d_seg + (size_t)(t - t0 - 1) * bytes;
+  };
+  for (int64_t t = t0; t + 1 < t1; ++t)
+    HIPCHK(launch_step(h->p.dtype, state(t), (char*)d_seg + (size_t)(t - t0) * bytes, h->links(),
+                       h->p.nx, h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream));
   for (int64_t t = t1 - 1; t >= t0; --t) {
-    scd_status st = adjoint_enqueue(h, (const char*)d_seg + (size_t)(t - t0) * bytes, lam[*lc],
-                                    lam[1 - *lc], true);
+    scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true);
     if (st) return st;
     *lc = 1 - *lc;
   }
   return SCD_OK;
+}
+
+// After a backward sweep the lattice holds the first checkpoint (step
+// ckpt_base), the start of the segment reversed last.
+static scd_status backward_finish(scd_lattice* h, const void* d_ckpt, double* h_grad) {
+  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_ckpt, bytes, hipMemcpyDeviceToDevice, h->stream));
+  h->step = h->ckpt_base;
+  return scd_adjoint_read(h, h_grad);
 }
 
 static scd_status backward_start(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
@@ -611,7 +621,7 @@ scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const vo
                          d_seg, lam, &lc);
     if (st) return st;
   }
-  return scd_adjoint_read(h, h_grad);
+  return backward_finish(h, d_ckpt, h_grad);
 }
 
 scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_t K2,
@@ -644,7 +654,7 @@ scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_
       if (st) return st;
     }
   }
-  return scd_adjoint_read(h, h_grad);
+  return backward_finish(h, d_ckpt, h_grad);
 }
 
 // ---------------------------------------------------------------- tiles
