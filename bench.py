@@ -139,6 +139,11 @@ def fp32_vs_fp64(scd, W, torch, steps, tile64, tile32, stream):
 
 
 def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
+    """Adjoint step against forward step on the gradient workload, both
+    launched the same way: one C call per step sequence, no graph, timed
+    with HIP events on the lattice's stream (the library captures forward
+    steps in graphs too; that time is reported as well)."""
+    import ctypes
     c = W.config_gradient(dtype=dtype)
     L = scd.Lattice(c["params"], c["solid"], adjoint=True, stream=stream)
     L.init_equilibrium(c["rho_a"], c["rho_b"])
@@ -147,22 +152,27 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
     lam = L.ca_seed(c["ca"], 1.0)
     lam2 = torch.empty_like(lam)
     L.graph_capture(20)
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    lib = scd.binding.lib()
+    p = scd.binding._ptr
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     torch.cuda.synchronize()
     e[0].record(stream)
     L.graph_replay(nsteps // 20)
     e[1].record(stream)
-    L.adjoint_reset()
+    scd.binding.check(lib.scd_step(L.h, ctypes.c_int64(nsteps)))
     e[2].record(stream)
+    L.adjoint_reset()
+    e[3].record(stream)
     a, b = lam, lam2
     for _ in range(nsteps):
-        L.adjoint_step(st, a, b, accumulate=True)
+        scd.binding.check(lib.scd_adjoint_step(L.h, p(st), p(a), p(b), None))
         a, b = b, a
-    e[3].record(stream)
+    e[4].record(stream)
     torch.cuda.synchronize()
     g = L.adjoint_read()
-    fwd = e[0].elapsed_time(e[1]) / nsteps
-    adj = e[2].elapsed_time(e[3]) / nsteps
+    fwd_graph = e[0].elapsed_time(e[1]) / nsteps
+    fwd = e[1].elapsed_time(e[2]) / nsteps
+    adj = e[3].elapsed_time(e[4]) / nsteps
     # the whole checkpointed gradient of the gradient workload: 2000 forward
     # steps with a checkpoint every 100, then the reverse sweep (segment
     # recompute + adjoint steps)
@@ -180,6 +190,7 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return {"workload": "64x64x48 droplet r=14, " + dtype, "forward_ms": round(fwd, 4),
+            "forward_graph_ms": round(fwd_graph, 4),
             "adjoint_ms": round(adj, 4), "ratio": round(adj / fwd, 3),
             "grad_finite": all(x == x for x in g),
             "checkpointed_2000_steps": {"forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
