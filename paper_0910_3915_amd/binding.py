@@ -266,6 +266,22 @@ class Lattice:
         check(lib().scd_set_state(self.h, _ptr(src), int(step)))
         self._keep = (src,)
 
+    def save(self, path):
+        """Checkpoint to a file: the post-collision state, the step counter,
+        the parameters and the solid mask (torch tensors and plain values,
+        readable with torch.load(..., weights_only=True))."""
+        torch.save({"state": self.get_state().cpu(), "step": int(self.step_count),
+                    "params": dict(self.params), "solid": self.solid.cpu()}, path)
+
+    @classmethod
+    def load(cls, path, device="cuda", adjoint=False, stream=None):
+        """A new lattice resumed from save(): continuing it reproduces the
+        uninterrupted run bit for bit."""
+        d = torch.load(path, weights_only=True)
+        lat = cls(d["params"], d["solid"].numpy(), device=device, adjoint=adjoint, stream=stream)
+        lat.set_state(d["state"], d["step"])
+        return lat
+
     def fill_state(self, value):
         check(lib().scd_fill_state(self.h, float(value)))
 
