@@ -146,7 +146,7 @@ namespace {
 // streaming stores, FP32 as the variant that issues all loads of a plane at
 // once (in FP64 that one needs 265 registers and falls to one wave).
 int default_variant(int dtype) {
-  int v = dtype == SCD_F64 ? variant_find(32, 8, 3, 2) : variant_find(32, 8, 5, 2);
+  int v = dtype == SCD_F64 ? variant_find(32, 4, 6, 1) : variant_find(64, 4, 6, 2);
   return v < 0 ? 0 : v;
 }
 
@@ -157,16 +157,31 @@ int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
-// z-chunk: the longest of 32, 16, 8, 4 planes that still gives every compute
-// unit a workgroup (long chunks re-pull fewer halo planes).
+// z-chunk from a wave-count model: each tile column is cut into chunks of zc
+// planes, a chunk reads zc + 2 planes, and the chunks run in rounds of one
+// workgroup per compute unit, so a step costs about rounds * (zc + 2) plane
+// times.  Every chunk count per column is tried with its shortest chunk
+// length (at least 4 planes); among those that give every compute unit a
+// workgroup the cheapest wins (the shorter chunk on a tie).  A lattice too
+// small to fill the chip takes 4-plane chunks.
 int default_zc(const scd_params& p, int variant) {
   int tx, ty, var, wpe;
   variant_at(variant, &tx, &ty, &var, &wpe);
   const long cols = (long)((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty);
-  const int cus = device_cus();
-  for (int zc : {32, 16, 8})
-    if (cols * ((p.nz + zc - 1) / zc) >= cus) return std::min(zc, p.nz);
-  return std::min(4, p.nz);
+  const long cus = device_cus();
+  int best = std::min(4, p.nz);
+  long best_cost = -1;
+  for (int nch = (p.nz + 3) / 4; nch >= 1; --nch) {
+    const int zc = (p.nz + nch - 1) / nch;
+    const long blocks = cols * ((p.nz + zc - 1) / zc);
+    if (blocks < cus) continue;
+    const long cost = (blocks + cus - 1) / cus * (zc + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
 }
 
 void default_tile(scd_lattice* h) {
@@ -768,7 +783,7 @@ scd_status scd_autotune(scd_lattice* h, int32_t steps_per_trial, const char* cac
   HIPCHK(hipEventCreate(&e1));
   double bms = 1e30;
   int b[2] = {h->variant, h->zc};
-  const int zcs[] = {4, 8, 16, 32, 64};
+  const int zcs[] = {4, 8, 16, 32, 64, 128};
   for (int i = 0; i < variant_count(); ++i) {
     int tx, ty, var, wpe;
     variant_at(i, &tx, &ty, &var, &wpe);

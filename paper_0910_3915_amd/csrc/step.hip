@@ -575,6 +575,201 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
 }
 
 // ---------------------------------------------------------------------------
+// Species-split z-march two planes at a time: each iteration issues the
+// loads of the next two planes (interior and halo) together, then collides
+// two planes after one barrier, so a wave keeps twice the bytes in flight
+// per memory latency and meets half as many barriers.  The e ring has 8
+// plane slots: an iteration writes the slots of its two new planes while
+// the previous iteration's collisions may still read the four before them.
+template <typename real, int TX, int TY>
+__device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, int by, int za,
+                                               int zb, real* __restrict__ lds, int dir = 1) {
+  using T = SplitTile<TX, TY>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int a = lane >> 5;
+  const int node = wave * 32 + (lane & 31);
+  const int tx = node % TX, ty = node / TX;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int x0 = bx * TX, y0 = by * TY;
+  const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  int xs[3], ys[3];
+  axis3(wrap_index(x0 + tx, nx), nx, xs);
+  axis3(wrap_index(y0 + ty, ny), ny, ys);
+  const int pos = (ty + 1) * T::LX + (tx + 1);
+  auto ring = [&](int zr, int c) { return lds + ((zr & 7) * 2 + c) * T::P; };
+
+  constexpr int HW = T::HPT * T::NT / 64;
+  int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
+  bool hval[T::HPT];
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) {
+    const int sl = tid + h * T::NT;
+    const int t = (sl & 63) * HW + (sl >> 6);
+    hval[h] = t < T::TASKS;
+    const int q = t >> 1;
+    hsp[h] = t & 1;
+    int lx, ly;
+    if (q < T::LX) { ly = -1; lx = q - 1; }
+    else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
+    else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
+    else { lx = TX; ly = q - 2 * T::LX - TY; }
+    if (!hval[h]) { lx = 0; ly = 0; }
+    axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
+    axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
+    hpos[h] = (ly + 1) * T::LX + (lx + 1);
+  }
+
+  // the march: plane j = 0 .. M + 1 in march order, interior planes 1 .. M
+  const int M = zb - za;
+  auto zof = [&](int j) { return dir > 0 ? za - 1 + j : zb - j; };
+  // link masks, two planes ahead
+  auto links_of = [&](int j, uint32_t& li, uint32_t(&lh)[T::HPT]) {
+    const int z = wrap_index(zof(j), nz);
+    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h)
+      lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
+  };
+
+  const real gab = L.ph.gab;
+  const int psi_form = L.ph.psi_form;
+  const real ew0 = L.ph.gw[1] * L.ph.psiw[0];
+  const real ew1 = L.ph.gw[0] * L.ph.psiw[1];
+  auto e_of = [&](int sp, bool wall, real rho) {
+    return wall ? (sp ? ew1 : ew0) : gab * psi_of(psi_form, rho);
+  };
+
+  // loads of plane j into n (interior) and hm (halo)
+  auto issue = [&](int j, uint32_t li, const uint32_t(&lh)[T::HPT], real(&n)[19],
+                   real(&hm)[T::HPT][19]) {
+    int zs[3];
+    axis3(wrap_index(zof(j), nz), nz, zs);
+    if (!(li & SELF_SOLID))
+      pull19(L.src, N, a, (zs[1] * ny + ys[1]) * nx + xs[1], xs, ys, zs, nx, ny, li, n);
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h)
+      if (!(lh[h] & SELF_SOLID))
+        pull19(L.src, N, hsp[h], (zs[1] * ny + hy[h][1]) * nx + hx[h][1], hx[h], hy[h], zs, nx,
+               ny, lh[h], hm[h]);
+  };
+  // densities of plane j -> e values into its ring slot
+  auto reduce = [&](int j, uint32_t li, const uint32_t(&lh)[T::HPT], const real(&n)[19],
+                    const real(&hm)[T::HPT][19]) {
+    const int zr = zof(j);
+    const bool wall = li & SELF_SOLID;
+    real r = 0;
+    if (!wall) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) r += n[k];
+    }
+    ring(zr, 1 - a)[pos] = e_of(a, wall, r);
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) {
+      if (!hval[h]) continue;
+      const bool hw = lh[h] & SELF_SOLID;
+      real rh = 0;
+      if (!hw) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) rh += hm[h][k];
+      }
+      ring(zr, 1 - hsp[h])[hpos[h]] = e_of(hsp[h], hw, rh);
+    }
+  };
+
+  const Phys<real>& ph = L.ph;
+  auto collide = [&](int zc, const real(&nc)[19], bool solid) {
+    real rho, jx, jy, jz;
+    moments(nc, rho, jx, jy, jz);
+    const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
+    const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
+    if (!active || solid) return;
+    const real* sm = ring(zc - 1, a);
+    const real* s0 = ring(zc, a);
+    const real* sp = ring(zc + 1, a);
+    real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const real* sl = CZ[k] < 0 ? sm : (CZ[k] > 0 ? sp : s0);
+      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+      const real e = w * sl[pos + CY[k] * T::LX + CX[k]];
+      if (CX[k]) sx += CX[k] * e;
+      if (CY[k]) sy += CY[k] * e;
+      if (CZ[k]) sz += CZ[k] * e;
+    }
+    const real psi_a = psi_of(ph.psi_form, rho);
+    const real rA = a ? rho_o : rho, rB = a ? rho : rho_o;
+    const real jAx = a ? jx_o : jx, jBx = a ? jx : jx_o;
+    const real jAy = a ? jy_o : jy, jBy = a ? jy : jy_o;
+    const real jAz = a ? jz_o : jz, jBz = a ? jz : jz_o;
+    const real itA = ph.inv_tau[0], itB = ph.inv_tau[1];
+    const real iR = real(1) / (rA * itA + rB * itB);
+    const real shf = ph.tau[a] / rho;
+    const real ux = (jAx * itA + jBx * itB) * iR + shf * (-psi_a * sx);
+    const real uy = (jAy * itA + jBy * itB) * iR + shf * (-psi_a * sy);
+    const real uz = (jAz * itA + jBz * itB) * iR + shf * (-psi_a * sz);
+    const real uu = ux * ux + uy * uy + uz * uz;
+    const real it = ph.inv_tau[a];
+    const int i = (zc * ny + ys[1]) * nx + xs[1];
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+    constexpr uint32_t S = sizeof(real);
+    real moving = 0;
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const int o = k + 1;
+      const real sdot = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+      real fk, fo;
+      equilibrium_pair(real(WEIGHT[k]) * rho, sdot, uu, fk, fo);
+      moving += fk + fo;
+      st_off_nt<real>(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, nc[k] + (fk - nc[k]) * it);
+      st_off_nt<real>(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, nc[o] + (fo - nc[o]) * it);
+    }
+    const real eq0 = rho - moving;
+    st_off_nt<real>(out, (uint32_t)i * S, nc[0] + (eq0 - nc[0]) * it);
+  };
+
+  // prologue: planes 0 and 1; masks of planes 2 and 3 requested
+  real nprev[19], n1[19], n2[19];
+  real hm1[T::HPT][19], hm2[T::HPT][19];
+  uint32_t l1, lh1[T::HPT], l2, lh2[T::HPT];
+  links_of(0, l1, lh1);
+  links_of(1, l2, lh2);
+  issue(0, l1, lh1, n1, hm1);
+  issue(1, l2, lh2, nprev, hm2);
+  reduce(0, l1, lh1, n1, hm1);
+  reduce(1, l2, lh2, nprev, hm2);
+  bool sprev = (l2 & SELF_SOLID) != 0;
+  uint32_t la, lha[T::HPT], lb = SELF_SOLID, lhb[T::HPT];
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) lhb[h] = SELF_SOLID;
+  links_of(2, la, lha);
+  if (M >= 2) links_of(3, lb, lhb);
+  // iteration: collide planes c and c + 1 (c = 1, 3, ...) after pulling
+  // planes c + 1 and c + 2
+  for (int c = 1; c <= M; c += 2) {
+    const bool two = c + 1 <= M;  // plane c + 1 is interior: pull c + 2 too
+    issue(c + 1, la, lha, n1, hm1);
+    if (two) issue(c + 2, lb, lhb, n2, hm2);
+    const uint32_t ua = la, ub = lb;
+    uint32_t uha[T::HPT], uhb[T::HPT];
+#pragma unroll
+    for (int h = 0; h < T::HPT; ++h) { uha[h] = lha[h]; uhb[h] = lhb[h]; }
+    if (c + 3 <= M + 1) links_of(c + 3, la, lha);
+    if (c + 4 <= M + 1) links_of(c + 4, lb, lhb);
+    reduce(c + 1, ua, uha, n1, hm1);
+    if (two) reduce(c + 2, ub, uhb, n2, hm2);
+    __syncthreads();
+    collide(zof(c), nprev, sprev);
+    if (two) {
+      collide(zof(c + 1), n1, (ua & SELF_SOLID) != 0);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) nprev[k] = n2[k];
+      sprev = (ub & SELF_SOLID) != 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Software-pipelined species-split z-march.  Iteration p issues the loads of
 // plane p (interior and halo), collides plane p - 2 while they are in
 // flight, then turns plane p into e values.  Collision of plane c needs e
@@ -758,13 +953,16 @@ constexpr int VAR_SPLIT_NT = 3;  // the same with streaming stores
 constexpr int VAR_PIPE = 4;      // software-pipelined species split, streaming stores
 constexpr int VAR_JOINT = 5;     // species split, streaming stores, all loads of a plane
                                  // (interior and halo) issued before any is used
+constexpr int VAR_DUAL = 6;      // species split, two planes per iteration
 
 template <typename real, int TX, int TY, int VAR>
 struct StepShape {
   static constexpr bool SPLIT =
-      VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT;
+      VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT ||
+      VAR == VAR_DUAL;
   static constexpr int THREADS = SPLIT ? 2 * TX * TY : TX * TY;
-  static constexpr int LDS_REALS = SPLIT ? 8 * SplitTile<TX, TY>::P : 8 * Tile<TX, TY>::P;
+  static constexpr int LDS_REALS = VAR == VAR_DUAL ? 16 * SplitTile<TX, TY>::P
+                                   : SPLIT ? 8 * SplitTile<TX, TY>::P : 8 * Tile<TX, TY>::P;
 };
 
 template <typename real, int TX, int TY, int VAR>
@@ -776,6 +974,8 @@ __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, 
     step_tile_split<real, TX, TY, true, false>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_JOINT)
     step_tile_split<real, TX, TY, true, true>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_DUAL)
+    step_tile_dual<real, TX, TY>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -953,7 +1153,7 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
 #define SCD_VARIANTS(X)                                                                   \
   X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
   X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 5, 1) X(32, 4, 5, 2) X(32, 8, 5, 2) \
-  X(64, 4, 5, 2)
+  X(64, 4, 5, 2) X(32, 8, 6, 2) X(32, 4, 6, 1) X(64, 4, 6, 2)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},

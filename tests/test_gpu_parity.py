@@ -74,7 +74,7 @@ def _variants():
 @pytest.mark.parametrize("variant", _variants())
 def test_ragged_box_every_variant(ragged_oracle, variant):
     c, ro = ragged_oracle
-    for zc in (4, 16, 23):
+    for zc in (4, 11, 16, 23):  # 23 = 11 + 11 + 1: a one-plane chunk
         announce(f"parity: ragged 70x37x23, variant {scd.tile_list()[variant]}, zchunk {zc}, 100 steps")
         L = _run_gpu(c, 100, tile=(variant, zc))
         d = np.max(np.abs(gpu_density(L) - ro))
