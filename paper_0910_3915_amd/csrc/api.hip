@@ -146,7 +146,7 @@ namespace {
 // streaming stores, FP32 as the variant that issues all loads of a plane at
 // once (in FP64 that one needs 265 registers and falls to one wave).
 int default_variant(int dtype) {
-  int v = dtype == SCD_F64 ? variant_find(32, 4, 6, 1) : variant_find(64, 4, 6, 2);
+  int v = dtype == SCD_F64 ? variant_find(32, 4, 7, 1) : variant_find(64, 4, 6, 2);
   return v < 0 ? 0 : v;
 }
 

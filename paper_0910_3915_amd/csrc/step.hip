@@ -575,16 +575,52 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
 }
 
 // ---------------------------------------------------------------------------
-// Species-split z-march two planes at a time: each iteration issues the
-// loads of the next two planes (interior and halo) together, then collides
-// two planes after one barrier, so a wave keeps twice the bytes in flight
-// per memory latency and meets half as many barriers.  The e ring has 8
-// plane slots: an iteration writes the slots of its two new planes while
-// the previous iteration's collisions may still read the four before them.
-template <typename real, int TX, int TY>
-__device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, int by, int za,
-                                               int zb, real* __restrict__ lds, int dir = 1) {
+// Species-split z-march G planes at a time: each iteration issues the loads
+// of the next G planes (interior and halo) together, then collides G planes
+// after one barrier, so a wave keeps G times the bytes in flight per memory
+// latency and meets one barrier per G planes.  The e ring has RS plane slots
+// (RS >= 2G + 2): an iteration writes the slots of its G new planes while
+// the previous iteration's collisions may still read the G + 2 before them.
+// Byte offsets of the nine columns (x + dx, y + dy) around a node within one
+// z plane, indexed [1 + dy][1 + dx]: with a plane's byte offset, every
+// neighbour of the node is one addition away.
+template <typename real>
+__device__ __forceinline__ void column_offsets(const int (&xs)[3], const int (&ys)[3], int nx,
+                                               uint32_t (&o)[3][3]) {
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+      o[dy][dx] = ((uint32_t)ys[dy] * (uint32_t)nx + (uint32_t)xs[dx]) * (uint32_t)sizeof(real);
+}
+
+// The pull of pull19 from precomputed column offsets and the byte offsets
+// zo of planes z - 1, z, z + 1: the neighbour and the bounce-back offsets
+// are each one addition, so the choice between them is a select.
+template <typename real>
+__device__ __forceinline__ void pull19_cols(const char* __restrict__ base, uint32_t NS,
+                                            const uint32_t (&col)[3][3], const uint32_t (&zo)[3],
+                                            uint32_t lb, real (&n)[19]) {
+  const uint32_t self = zo[1] + col[1][1];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const uint32_t nb = (uint32_t)k * NS + zo[1 - CZ[k]] + col[1 - CY[k]][1 - CX[k]];
+    const uint32_t bb = (uint32_t)OPP[k] * NS + self;
+    n[k] = ld_off<real>(base, ((lb >> OPP[k]) & 1u) ? bb : nb);
+  }
+}
+
+template <int G>
+struct MultiRing {
+  static constexpr int RS = G <= 3 ? 8 : 16;
+  static_assert(RS >= 2 * G + 2, "ring too short for the planes in flight");
+};
+
+template <typename real, int TX, int TY, int G>
+__device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, int by, int za,
+                                                int zb, real* __restrict__ lds, int dir = 1) {
   using T = SplitTile<TX, TY>;
+  constexpr int RS = MultiRing<G>::RS;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int a = lane >> 5;
@@ -597,7 +633,7 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
   axis3(wrap_index(x0 + tx, nx), nx, xs);
   axis3(wrap_index(y0 + ty, ny), ny, ys);
   const int pos = (ty + 1) * T::LX + (tx + 1);
-  auto ring = [&](int zr, int c) { return lds + ((zr & 7) * 2 + c) * T::P; };
+  auto ring = [&](int zr, int c) { return lds + ((zr & (RS - 1)) * 2 + c) * T::P; };
 
   constexpr int HW = T::HPT * T::NT / 64;
   int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
@@ -620,22 +656,37 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
     hpos[h] = (ly + 1) * T::LX + (lx + 1);
   }
 
+  // byte offsets: one species (NS), one z plane (PS), the columns around the
+  // thread's node and halo nodes; per-species bases of the source state
+  constexpr uint32_t S = sizeof(real);
+  const uint32_t NS = (uint32_t)N * S, PS = (uint32_t)(nx * ny) * S;
+  uint32_t col[3][3], hcol[T::HPT][3][3];
+  column_offsets<real>(xs, ys, nx, col);
+  const char* __restrict__ sbase = reinterpret_cast<const char*>(L.src + (size_t)a * Q * N);
+  const char* __restrict__ hbase[T::HPT];
+  int hidx[T::HPT];
+#pragma unroll
+  for (int h = 0; h < T::HPT; ++h) {
+    column_offsets<real>(hx[h], hy[h], nx, hcol[h]);
+    hbase[h] = reinterpret_cast<const char*>(L.src + (size_t)hsp[h] * Q * N);
+    hidx[h] = hy[h][1] * nx + hx[h][1];
+  }
+  const int cidx = ys[1] * nx + xs[1];
+
   // the march: plane j = 0 .. M + 1 in march order, interior planes 1 .. M
   const int M = zb - za;
   auto zof = [&](int j) { return dir > 0 ? za - 1 + j : zb - j; };
-  // link masks, two planes ahead
   auto links_of = [&](int j, uint32_t& li, uint32_t(&lh)[T::HPT]) {
-    const int z = wrap_index(zof(j), nz);
-    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+    const int zn = wrap_index(zof(j), nz) * nx * ny;
+    li = L.links[zn + cidx];
 #pragma unroll
-    for (int h = 0; h < T::HPT; ++h)
-      lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
+    for (int h = 0; h < T::HPT; ++h) lh[h] = hval[h] ? L.links[zn + hidx[h]] : SELF_SOLID;
   };
 
   const real gab = L.ph.gab;
   const int psi_form = L.ph.psi_form;
-  const real ew0 = L.ph.gw[1] * L.ph.psiw[0];
-  const real ew1 = L.ph.gw[0] * L.ph.psiw[1];
+  const real ew0 = L.ph.gw[1] * L.ph.psiw[0];  // e written by a wall thread of species 0
+  const real ew1 = L.ph.gw[0] * L.ph.psiw[1];  // ... of species 1
   auto e_of = [&](int sp, bool wall, real rho) {
     return wall ? (sp ? ew1 : ew0) : gab * psi_of(psi_form, rho);
   };
@@ -645,13 +696,11 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
                    real(&hm)[T::HPT][19]) {
     int zs[3];
     axis3(wrap_index(zof(j), nz), nz, zs);
-    if (!(li & SELF_SOLID))
-      pull19(L.src, N, a, (zs[1] * ny + ys[1]) * nx + xs[1], xs, ys, zs, nx, ny, li, n);
+    const uint32_t zo[3] = {(uint32_t)zs[0] * PS, (uint32_t)zs[1] * PS, (uint32_t)zs[2] * PS};
+    if (!(li & SELF_SOLID)) pull19_cols<real>(sbase, NS, col, zo, li, n);
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h)
-      if (!(lh[h] & SELF_SOLID))
-        pull19(L.src, N, hsp[h], (zs[1] * ny + hy[h][1]) * nx + hx[h][1], hx[h], hy[h], zs, nx,
-               ny, lh[h], hm[h]);
+      if (!(lh[h] & SELF_SOLID)) pull19_cols<real>(hbase[h], NS, hcol[h], zo, lh[h], hm[h]);
   };
   // densities of plane j -> e values into its ring slot
   auto reduce = [&](int j, uint32_t li, const uint32_t(&lh)[T::HPT], const real(&n)[19],
@@ -679,11 +728,13 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
 
   const Phys<real>& ph = L.ph;
   auto collide = [&](int zc, const real(&nc)[19], bool solid) {
+    // every lane takes part in the swap; inactive and wall lanes carry junk
     real rho, jx, jy, jz;
     moments(nc, rho, jx, jy, jz);
     const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
     const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
     if (!active || solid) return;
+    // Eq. (SCforce) on species a: S^a = sum_k W_k e^a(x + c_k) c_k
     const real* sm = ring(zc - 1, a);
     const real* s0 = ring(zc, a);
     const real* sp = ring(zc + 1, a);
@@ -698,6 +749,8 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
       if (CZ[k]) sz += CZ[k] * e;
     }
     const real psi_a = psi_of(ph.psi_form, rho);
+    // the common velocity, with the two species in a fixed order so that
+    // both halves of the wave compute the same value
     const real rA = a ? rho_o : rho, rB = a ? rho : rho_o;
     const real jAx = a ? jx_o : jx, jBx = a ? jx : jx_o;
     const real jAy = a ? jy_o : jy, jBy = a ? jy : jy_o;
@@ -710,9 +763,8 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
     const real uz = (jAz * itA + jBz * itB) * iR + shf * (-psi_a * sz);
     const real uu = ux * ux + uy * uy + uz * uz;
     const real it = ph.inv_tau[a];
-    const int i = (zc * ny + ys[1]) * nx + xs[1];
+    const uint32_t iS = (uint32_t)zc * PS + col[1][1];
     char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
-    constexpr uint32_t S = sizeof(real);
     real moving = 0;
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
@@ -721,51 +773,67 @@ __device__ __forceinline__ void step_tile_dual(const LatDev<real>& L, int bx, in
       real fk, fo;
       equilibrium_pair(real(WEIGHT[k]) * rho, sdot, uu, fk, fo);
       moving += fk + fo;
-      st_off_nt<real>(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, nc[k] + (fk - nc[k]) * it);
-      st_off_nt<real>(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, nc[o] + (fo - nc[o]) * it);
+      st_off_nt<real>(out, (uint32_t)k * NS + iS, nc[k] + (fk - nc[k]) * it);
+      st_off_nt<real>(out, (uint32_t)o * NS + iS, nc[o] + (fo - nc[o]) * it);
     }
     const real eq0 = rho - moving;
-    st_off_nt<real>(out, (uint32_t)i * S, nc[0] + (eq0 - nc[0]) * it);
+    st_off_nt<real>(out, iS, nc[0] + (eq0 - nc[0]) * it);
   };
 
-  // prologue: planes 0 and 1; masks of planes 2 and 3 requested
-  real nprev[19], n1[19], n2[19];
-  real hm1[T::HPT][19], hm2[T::HPT][19];
-  uint32_t l1, lh1[T::HPT], l2, lh2[T::HPT];
-  links_of(0, l1, lh1);
-  links_of(1, l2, lh2);
-  issue(0, l1, lh1, n1, hm1);
-  issue(1, l2, lh2, nprev, hm2);
-  reduce(0, l1, lh1, n1, hm1);
-  reduce(1, l2, lh2, nprev, hm2);
-  bool sprev = (l2 & SELF_SOLID) != 0;
-  uint32_t la, lha[T::HPT], lb = SELF_SOLID, lhb[T::HPT];
+  // n[0]: the plane collided first in an iteration; n[g]: plane c + g
+  real n[G + 1][19];
+  real hm[G][T::HPT][19];
+  bool solid[G + 1];
+  uint32_t lk[G], lkh[G][T::HPT];
 #pragma unroll
-  for (int h = 0; h < T::HPT; ++h) lhb[h] = SELF_SOLID;
-  links_of(2, la, lha);
-  if (M >= 2) links_of(3, lb, lhb);
-  // iteration: collide planes c and c + 1 (c = 1, 3, ...) after pulling
-  // planes c + 1 and c + 2
-  for (int c = 1; c <= M; c += 2) {
-    const bool two = c + 1 <= M;  // plane c + 1 is interior: pull c + 2 too
-    issue(c + 1, la, lha, n1, hm1);
-    if (two) issue(c + 2, lb, lhb, n2, hm2);
-    const uint32_t ua = la, ub = lb;
-    uint32_t uha[T::HPT], uhb[T::HPT];
+  for (int g = 0; g < G; ++g) {
+    lk[g] = SELF_SOLID;
 #pragma unroll
-    for (int h = 0; h < T::HPT; ++h) { uha[h] = lha[h]; uhb[h] = lhb[h]; }
-    if (c + 3 <= M + 1) links_of(c + 3, la, lha);
-    if (c + 4 <= M + 1) links_of(c + 4, lb, lhb);
-    reduce(c + 1, ua, uha, n1, hm1);
-    if (two) reduce(c + 2, ub, uhb, n2, hm2);
-    __syncthreads();
-    collide(zof(c), nprev, sprev);
-    if (two) {
-      collide(zof(c + 1), n1, (ua & SELF_SOLID) != 0);
+    for (int h = 0; h < T::HPT; ++h) lkh[g][h] = SELF_SOLID;
+  }
+  // prologue: planes 0 and 1 (plane 0 only feeds e values), masks of 2 .. G + 1
+  {
+    uint32_t l0, lh0[T::HPT], l1, lh1[T::HPT];
+    links_of(0, l0, lh0);
+    links_of(1, l1, lh1);
+    issue(0, l0, lh0, n[1], hm[0]);
+    issue(1, l1, lh1, n[0], hm[G - 1]);
+    reduce(0, l0, lh0, n[1], hm[0]);
+    reduce(1, l1, lh1, n[0], hm[G - 1]);
+    solid[0] = (l1 & SELF_SOLID) != 0;
+  }
 #pragma unroll
-      for (int k = 0; k < Q; ++k) nprev[k] = n2[k];
-      sprev = (ub & SELF_SOLID) != 0;
+  for (int g = 0; g < G; ++g)
+    if (2 + g <= M + 1) links_of(2 + g, lk[g], lkh[g]);
+  // iteration: pull planes c + 1 .. c + G, collide planes c .. c + G - 1
+  for (int c = 1; c <= M; c += G) {
+    uint32_t u[G], uh[G][T::HPT];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      u[g] = lk[g];
+#pragma unroll
+      for (int h = 0; h < T::HPT; ++h) uh[g][h] = lkh[g][h];
     }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + g <= M + 1) issue(c + 1 + g, u[g], uh[g], n[1 + g], hm[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + G + g <= M + 1) links_of(c + 1 + G + g, lk[g], lkh[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + g <= M + 1) {
+        reduce(c + 1 + g, u[g], uh[g], n[1 + g], hm[g]);
+        solid[1 + g] = (u[g] & SELF_SOLID) != 0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + g <= M) collide(zof(c + g), n[g], solid[g]);
+    // plane c + G opens the next iteration
+#pragma unroll
+    for (int k = 0; k < Q; ++k) n[0][k] = n[G][k];
+    solid[0] = solid[G];
   }
 }
 
@@ -954,15 +1022,21 @@ constexpr int VAR_PIPE = 4;      // software-pipelined species split, streaming 
 constexpr int VAR_JOINT = 5;     // species split, streaming stores, all loads of a plane
                                  // (interior and halo) issued before any is used
 constexpr int VAR_DUAL = 6;      // species split, two planes per iteration
+constexpr int VAR_TRIPLE = 7;    // species split, three planes per iteration
+constexpr int VAR_QUAD = 8;      // species split, four planes per iteration
 
 template <typename real, int TX, int TY, int VAR>
 struct StepShape {
   static constexpr bool SPLIT =
       VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT ||
-      VAR == VAR_DUAL;
+      VAR == VAR_DUAL || VAR == VAR_TRIPLE || VAR == VAR_QUAD;
   static constexpr int THREADS = SPLIT ? 2 * TX * TY : TX * TY;
-  static constexpr int LDS_REALS = VAR == VAR_DUAL ? 16 * SplitTile<TX, TY>::P
-                                   : SPLIT ? 8 * SplitTile<TX, TY>::P : 8 * Tile<TX, TY>::P;
+  static constexpr int LDS_REALS =
+      VAR == VAR_DUAL     ? 2 * MultiRing<2>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_TRIPLE ? 2 * MultiRing<3>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_QUAD   ? 2 * MultiRing<4>::RS * SplitTile<TX, TY>::P
+      : SPLIT             ? 8 * SplitTile<TX, TY>::P
+                          : 8 * Tile<TX, TY>::P;
 };
 
 template <typename real, int TX, int TY, int VAR>
@@ -975,7 +1049,11 @@ __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, 
   else if constexpr (VAR == VAR_JOINT)
     step_tile_split<real, TX, TY, true, true>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_DUAL)
-    step_tile_dual<real, TX, TY>(L, bx, by, za, zb, lds, dir);
+    step_tile_multi<real, TX, TY, 2>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_TRIPLE)
+    step_tile_multi<real, TX, TY, 3>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_QUAD)
+    step_tile_multi<real, TX, TY, 4>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -1153,7 +1231,8 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
 #define SCD_VARIANTS(X)                                                                   \
   X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
   X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 5, 1) X(32, 4, 5, 2) X(32, 8, 5, 2) \
-  X(64, 4, 5, 2) X(32, 8, 6, 2) X(32, 4, 6, 1) X(64, 4, 6, 2)
+  X(64, 4, 5, 2) X(32, 8, 6, 2) X(32, 4, 6, 1) X(64, 4, 6, 2) X(32, 4, 7, 1) X(64, 4, 7, 2) \
+  X(32, 4, 8, 1)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},
