@@ -60,13 +60,36 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
                                                    const real* __restrict__ rhof, int nx, int ny,
                                                    int nz, Phys<real> ph, real* __restrict__ qf,
                                                    real* __restrict__ df, real* __restrict__ ef,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials, int accumulate) {
   __shared__ double sh[5 * 16];
   const int N = nx * ny * nz;
+  const int stride = gridDim.x * blockDim.x;
   double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    const uint32_t lb = links[i];
+  // The FP64 kernel holds one wave per SIMD, so nothing else hides its load
+  // latency: the next node's populations are requested once this node's
+  // neighbour densities are in, and arrive while its lambda' is read and
+  // its collision transposed.
+  constexpr bool PREFETCH = sizeof(real) == 8;
+  auto fetch = [&](int node, uint32_t& l, real(&c)[38]) {
+    l = links[node];
+    if (!(l & SELF_SOLID)) {
+      int xs[3], ys[3], zs[3];
+      axis3(node % nx, nx, xs);
+      axis3((node / nx) % ny, ny, ys);
+      axis3(node / (nx * ny), nz, zs);
+      pull38_adj(C, N, node, xs, ys, zs, nx, ny, l, c);
+    }
+  };
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  real n[38];
+  uint32_t lnext = SELF_SOLID;
+  if (PREFETCH && i < N) fetch(i, lnext, n);
+  for (; i < N; i += stride) {
+    uint32_t lb;
+    if (PREFETCH) lb = lnext;
+    else lb = links[i];
     if (lb & SELF_SOLID) {
+      if (PREFETCH && i + stride < N) fetch(i + stride, lnext, n);
       for (int c = 0; c < 6; ++c) { qf[(size_t)c * N + i] = 0; ef[(size_t)c * N + i] = 0; }
       df[i] = 0;
       df[(size_t)N + i] = 0;
@@ -76,15 +99,19 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
-    real n[38];
-    pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
+    if (!PREFETCH) pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
     real rho[2], j[2][3];
     moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
     moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
     real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
-    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k
+    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k.
+    // For the parameter gradient the FP32 kernel keeps psi at every
+    // neighbour; the FP64 kernel, short of registers, keeps the sums
+    // T^b = sum over fluid neighbours of W_k psi^b(y) c_k (the g_ab part of
+    // S) and V = sum over wall neighbours of W_k c_k (the wall part).
     real S[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    real pnb[Q][2];  // psi of both species at each neighbour (wall content at walls)
+    real T[2][3] = {{0, 0, 0}, {0, 0, 0}}, V[3] = {0, 0, 0};
+    real pnb[PREFETCH ? 1 : Q][2];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const bool wall = (lb >> k) & 1u;
@@ -97,14 +124,23 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
         pA = psi_of(ph.psi_form, rhof[y]);
         pB = psi_of(ph.psi_form, rhof[(size_t)N + y]);
       }
-      pnb[k][0] = pA;
-      pnb[k][1] = pB;
       const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
       const real eA = w * (wall ? ph.gw[0] : ph.gab) * pB;
       const real eB = w * (wall ? ph.gw[1] : ph.gab) * pA;
       S[0][0] += CX[k] * eA; S[0][1] += CY[k] * eA; S[0][2] += CZ[k] * eA;
       S[1][0] += CX[k] * eB; S[1][1] += CY[k] * eB; S[1][2] += CZ[k] * eB;
+      if constexpr (PREFETCH) {
+        const real wA = wall ? real(0) : w * pA, wB = wall ? real(0) : w * pB;
+        const real ww = wall ? w : real(0);
+        if (CX[k]) { T[0][0] += CX[k] * wA; T[1][0] += CX[k] * wB; V[0] += CX[k] * ww; }
+        if (CY[k]) { T[0][1] += CY[k] * wA; T[1][1] += CY[k] * wB; V[1] += CY[k] * ww; }
+        if (CZ[k]) { T[0][2] += CZ[k] * wA; T[1][2] += CZ[k] * wB; V[2] += CZ[k] * ww; }
+      } else {
+        pnb[k][0] = pA;
+        pnb[k][1] = pB;
+      }
     }
+    if (PREFETCH && i + stride < N) fetch(i + stride, lnext, n);
     real F[2][3];
     for (int a = 0; a < 2; ++a)
       for (int d = 0; d < 3; ++d) F[a][d] = -psi[a] * S[a][d];
@@ -160,23 +196,38 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       const real dpsi_self = -(dF[a][0] * S[a][0] + dF[a][1] * S[a][1] + dF[a][2] * S[a][2]);
       for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi[a] * dF[a][d];
       df[(size_t)a * N + i] = drho[a] + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
+      if constexpr (PREFETCH) {
+        // F^a = -psi^a S^a with S^a = g_ab T^b + g_wall^a psi_wall^b V
+        const double m = -(double)psi[a];
+        const double dTF = m * ((double)dF[a][0] * T[b][0] + (double)dF[a][1] * T[b][1] +
+                                (double)dF[a][2] * T[b][2]);
+        const double dV = m * ((double)dF[a][0] * V[0] + (double)dF[a][1] * V[1] +
+                               (double)dF[a][2] * V[2]);
+        gp[2] += dTF;
+        gp[3 + a] += (double)ph.psiw[b] * dV;
+        gp[b] += (double)ph.gw[a] * dV * (double)ph.dpsiw[b];
+      } else {
 #pragma unroll
-      for (int k = 1; k < Q; ++k) {
-        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-        const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
-        const double t = (double)(-psi[a] * w * dFc);
-        if ((lb >> k) & 1u) {
-          gp[3 + a] += (double)ph.psiw[b] * t;
-          gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
-        } else {
-          gp[2] += (double)pnb[k][b] * t;
+        for (int k = 1; k < Q; ++k) {
+          const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+          const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
+          const double t = (double)(-psi[a] * w * dFc);
+          if ((lb >> k) & 1u) {
+            gp[3 + a] += (double)ph.psiw[b] * t;
+            gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
+          } else {
+            gp[2] += (double)pnb[k][b] * t;
+          }
         }
       }
     }
   }
   block_sum_adj<5>(gp, sh);
+  // a block owns its slot, so accumulating over steps is deterministic
   if (threadIdx.x == 0)
-    for (int c = 0; c < 5; ++c) partials[blockIdx.x * RED_STRIDE + c] = gp[c];
+    for (int c = 0; c < 5; ++c)
+      partials[blockIdx.x * RED_STRIDE + c] =
+          accumulate ? partials[blockIdx.x * RED_STRIDE + c] + gp[c] : gp[c];
 }
 
 // D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b
@@ -200,9 +251,11 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
       const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const real qc = qf[(size_t)(a * 3 + 0) * N + x] * CX[k] +
-                        qf[(size_t)(a * 3 + 1) * N + x] * CY[k] +
-                        qf[(size_t)(a * 3 + 2) * N + x] * CZ[k];
+        // only the components along which c_k moves (60 of the 108 loads)
+        real qc = 0;
+        if (CX[k]) qc += qf[(size_t)(a * 3 + 0) * N + x] * CX[k];
+        if (CY[k]) qc += qf[(size_t)(a * 3 + 1) * N + x] * CY[k];
+        if (CZ[k]) qc += qf[(size_t)(a * 3 + 2) * N + x] * CZ[k];
         acc[1 - a] += w * qc;
       }
     }
@@ -271,13 +324,13 @@ template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                             const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
                             real* rhof, real* qf, real* df, real* ef, double* partials,
-                            double* dparams, hipStream_t s) {
+                            int accumulate, hipStream_t s) {
   const Phys<real> ph = phys_cast<real>(phd);
   const size_t N = (size_t)nx * ny * nz;
   hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, C,
-                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials);
+                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny, nz,
                      ph, qf, df);
@@ -292,19 +345,30 @@ __global__ void k_sum5(const double* __restrict__ partials, int nblocks, double*
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
                           void* rho_field, void* q_field, void* d_field, void* e_field,
-                          double* partials, double* dparams_dev, double* acc, hipStream_t s) {
+                          double* partials, double* dparams_dev, double* acc_partials,
+                          hipStream_t s) {
+  // with acc_partials the block partials accumulate over steps and are summed
+  // only when read (launch_adjoint_sum); otherwise this step's sum goes to
+  // dparams_dev
+  double* part = acc_partials ? acc_partials : partials;
+  const int accumulate = acc_partials != nullptr;
   hipError_t e;
   if (dtype == 0)
     e = adjoint_t<double>((const double*)state_t, (const double*)lam_in, (double*)lam_out, links,
                           nx, ny, nz, ph, (double*)rho_field, (double*)q_field, (double*)d_field,
-                          (double*)e_field, partials, dparams_dev, s);
+                          (double*)e_field, part, accumulate, s);
   else
     e = adjoint_t<float>((const float*)state_t, (const float*)lam_in, (float*)lam_out, links, nx,
                          ny, nz, ph, (float*)rho_field, (float*)q_field, (float*)d_field,
-                         (float*)e_field, partials, dparams_dev, s);
+                         (float*)e_field, part, accumulate, s);
   if (e != hipSuccess) return e;
+  if (accumulate) return hipSuccess;
+  return launch_adjoint_sum(dtype, partials, dparams_dev, s);
+}
+
+hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum5, dim3(1), dim3(256), 0, s, partials, adj_local_grid(dtype == 0 ? 8 : 4),
-                     dparams_dev, acc);
+                     out, nullptr);
   return hipGetLastError();
 }
 
@@ -328,7 +392,7 @@ __global__ void k_zero(double* __restrict__ p, int n) {
 }
 
 hipError_t launch_zero(double* p, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, p, n);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t real_size(int dtype) { return dtype == SCD_F64 ? 8 : 4; }
 
 struct WorkLayout {
-  size_t links, partials, result, phi, ca, planes, rho, adj_partials, adj_dparams, q, d, e, total;
+  size_t links, partials, result, phi, ca, planes, rho, adj_partials, adj_acc, adj_dparams, q, d, e,
+      total;
 };
 
 WorkLayout work_layout(const scd_params* p) {
@@ -64,6 +65,7 @@ WorkLayout work_layout(const scd_params* p) {
   w.rho = take(2 * N * rs);            // post-stream densities (pressure, adjoint)
   if (p->flags & SCD_WITH_ADJOINT) {
     w.adj_partials = take((size_t)ADJ_BLOCKS * RED_STRIDE * 8);
+    w.adj_acc = take((size_t)ADJ_BLOCKS * RED_STRIDE * 8);  // partials summed over steps
     w.adj_dparams = take(16 * 8);  // [0, 8): last step, [8, 16): accumulator
     w.q = take(6 * N * rs);
     w.d = take(2 * N * rs);
@@ -495,7 +497,7 @@ static scd_status adjoint_enqueue(scd_lattice* h, const void* state_t, const voi
   HIPCHK(launch_adjoint(h->p.dtype, state_t, lam_in, lam_out, h->links(), h->p.nx, h->p.ny,
                         h->p.nz, h->ph, h->wv(h->wl.rho), h->wv(h->wl.q), h->wv(h->wl.d),
                         h->wv(h->wl.e), h->wd(h->wl.adj_partials), h->wd(h->wl.adj_dparams),
-                        accumulate ? h->wd(h->wl.adj_dparams) + 8 : nullptr, h->stream));
+                        accumulate ? h->wd(h->wl.adj_acc) : nullptr, h->stream));
   return SCD_OK;
 }
 
@@ -503,7 +505,7 @@ scd_status scd_adjoint_reset(scd_lattice* h) {
   if (!h) return fail(SCD_EINVAL, "NULL handle");
   if (!(h->p.flags & SCD_WITH_ADJOINT))
     return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
-  HIPCHK(launch_zero(h->wd(h->wl.adj_dparams) + 8, 8, h->stream));
+  HIPCHK(launch_zero(h->wd(h->wl.adj_acc), ADJ_BLOCKS * RED_STRIDE, h->stream));
   return SCD_OK;
 }
 
@@ -511,6 +513,8 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc) {
   if (!h || !h_acc) return fail(SCD_EINVAL, "NULL argument");
   if (!(h->p.flags & SCD_WITH_ADJOINT))
     return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
+  HIPCHK(launch_adjoint_sum(h->p.dtype, h->wd(h->wl.adj_acc), h->wd(h->wl.adj_dparams) + 8,
+                            h->stream));
   HIPCHK(hipMemcpyAsync(h_acc, h->wd(h->wl.adj_dparams) + 8, 5 * sizeof(double),
                         hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

@@ -76,10 +76,16 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
 
 // adjoint.hip
 constexpr int ADJ_BLOCKS = 2048;
+// One reverse step.  acc_partials == nullptr: this step's parameter gradient
+// is summed into dparams_dev[0..5).  Otherwise the per-workgroup partials
+// accumulate in acc_partials (ADJ_BLOCKS x RED_STRIDE doubles, zeroed by the
+// caller) and launch_adjoint_sum reduces them when they are read.
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
                           void* rho_field, void* q_field, void* d_field, void* e_field,
-                          double* partials, double* dparams_dev, double* acc, hipStream_t s);
+                          double* partials, double* dparams_dev, double* acc_partials,
+                          hipStream_t s);
+hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s);
 hipError_t launch_zero(double* p, int n, hipStream_t s);
 
 }  // namespace scd
