@@ -252,25 +252,34 @@ def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):
             "speedup": round(ts / tb, 3)}
 
 
-def copy_probe(torch, stream, nbytes=1 << 30, reps=20):
-    """Attainable HBM bandwidth: a plain device-to-device copy of nbytes
-    (read + write counted), timed with events on the same stream."""
+def copy_probe(torch, scd, stream, nbytes=1 << 30, reps=20):
+    """Attainable HBM bandwidth of a read-once write-once sweep: the library's
+    STREAM copy kernel over nbytes (read + write counted), timed with events
+    on the same stream; torch's own device copy is reported beside it."""
     n = nbytes // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        dst.copy_(src)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            dst.copy_(src)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return {"bytes_per_copy": 2 * n * 8, "us": round(ms * 1e3, 2),
-            "GBs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(lambda: scd.stream_copy(src, dst, stream))
+    if not torch.equal(src, dst):
+        raise RuntimeError("STREAM copy probe produced a wrong copy")
+    ms_torch = timed(lambda: dst.copy_(src))
+    return {"bytes_per_copy": 2 * n * 8, "kernel": "k_stream_copy", "us": round(ms * 1e3, 2),
+            "GBs": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1),
+            "torch_copy_GBs": round(2 * n * 8 / (ms_torch * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(W, seconds):
@@ -354,7 +363,7 @@ def main():
                              "f32": adjoint_cost(scd, W, torch, stream, "f32")}
         log("batched vs sequential")
         result["batched"] = batched_vs_sequential(scd, W, torch, stream)
-    result["copy_probe"] = copy_probe(torch, stream)
+    result["copy_probe"] = copy_probe(torch, scd, stream)
     log("copy probe", result["copy_probe"])
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -264,13 +264,18 @@ scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_
                               const scd_ca_cfg* cfg, double target_deg, double* h_grad);
 
 /* ---- launch control (extension) ---- */
-/* The fused step is compiled in several variants: a tile of tx * ty
- * threads (one column each), a z-march variant (0: the collided plane's
- * populations stay in registers; 1: they are pulled again from cache, which
- * frees registers) and a minimum number of waves per SIMD.  scd_tile_list
+/* The fused step is compiled in several variants: a tile of tx * ty node
+ * columns marched along z, a z-march variant and a minimum number of waves
+ * per SIMD.  z-march variants: 0 one thread per node, populations kept in
+ * registers; 1 the same, pulled again from cache at the collision; 2 two
+ * threads per node (one per species); 3 as 2 with streaming stores; 4 as 3,
+ * software-pipelined; 5 as 3 with all loads of a plane issued together;
+ * 6, 7, 8 as 5 with two, three or four planes per barrier.  scd_tile_list
  * writes up to cap rows (tx, ty, z-march variant, waves) into h_rows (4
  * int32 per row) and the number of variants into *n.  A lattice uses one
- * variant index and a z-chunk of zc planes per workgroup. */
+ * variant index and a z-chunk of zc planes per workgroup; the default is
+ * variant 7 (32 x 4, one wave) in FP64 and 6 (64 x 4, two waves) in FP32,
+ * with zc from a model of workgroup rounds. */
 scd_status scd_tile_list(int32_t* h_rows, int32_t cap, int32_t* n);
 scd_status scd_tile_set(scd_lattice* h, int32_t variant, int32_t zc);
 scd_status scd_tile_get(const scd_lattice* h, int32_t* variant, int32_t* zc);
@@ -325,6 +330,13 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
 /* Fill each of the 38 * N entries of the current state with value
  * (for tests of the observables) */
 scd_status scd_fill_state(scd_lattice* h, double value);
+
+/* Measurement helper: copy bytes (a multiple of 8) from d_src to d_dst
+ * (device, 8-byte aligned, not overlapping) with a plain grid-stride copy
+ * kernel on the stream (may be NULL for the default stream); asynchronous.
+ * Timed by the caller, it gives the attainable HBM rate of a read-once
+ * write-once sweep: the ceiling the fused step's rate is compared with. */
+scd_status scd_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
 
 const char* scd_last_error(void);
 const char* scd_version(void);

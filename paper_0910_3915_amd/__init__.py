@@ -5,5 +5,5 @@ The compute path is the C-ABI library ``libscdrop.so`` (include/scdrop.h);
 this package only binds it.  PyTorch supplies device memory and streams.
 """
 from .binding import (Batch, Lattice, ScdError, check, header_symbols, lib,  # noqa: F401
-                      make_ca_cfg, make_params, tile_list, variant_index)
+                      make_ca_cfg, make_params, stream_copy, tile_list, variant_index)
 from .grad import ContactAngleFn, GradSetup  # noqa: F401

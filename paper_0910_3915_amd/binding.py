@@ -104,6 +104,7 @@ _PROTOS = {
     "scd_batch_graph_capture": [_VP, _I64],
     "scd_batch_graph_replay": [_VP, _I64],
     "scd_batch_autotune": [_VP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_D)],
+    "scd_stream_copy": [_VP, _VP, ctypes.c_size_t, _VP],
 }
 
 
@@ -407,6 +408,15 @@ def huang_angle(params, rho_in, rho_out):
     """Huang's estimate (Eq. huangSigmaLG) for droplet species A, degrees."""
     sp = make_params(params)
     return lib().scd_huang_angle(ctypes.byref(sp), float(rho_in), float(rho_out))
+
+
+def stream_copy(src, dst, stream=None):
+    """Copy device tensor src into dst (same byte size, a multiple of 8) with
+    the library's STREAM copy kernel on stream; asynchronous."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("source and destination sizes differ")
+    check(lib().scd_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream_handle(stream)))
 
 
 def tile_list():

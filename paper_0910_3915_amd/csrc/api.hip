@@ -243,6 +243,18 @@ scd_status read_ca(scd_lattice* h, scd_ca* out, double* status_out) {
 
 extern "C" {
 
+scd_status scd_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+  if (!d_src || !d_dst) return fail(SCD_EINVAL, "NULL pointer");
+  if (bytes % 8 || ((uintptr_t)d_src | (uintptr_t)d_dst) % 8)
+    return fail(SCD_EINVAL, "size and pointers must be multiples of 8 bytes");
+  const uintptr_t a = (uintptr_t)d_src, b = (uintptr_t)d_dst;
+  if (a < b + bytes && b < a + bytes) return fail(SCD_EINVAL, "source and destination overlap");
+  if (bytes == 0) return SCD_OK;
+  HIPCHK(launch_stream_copy((const double*)d_src, (double*)d_dst, bytes / 8,
+                            (hipStream_t)stream));
+  return SCD_OK;
+}
+
 const char* scd_last_error(void) { return g_err.c_str(); }
 const char* scd_version(void) { return "scdrop 1.0 (gfx950)"; }
 

@@ -586,4 +586,20 @@ hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, c
   return hipGetLastError();
 }
 
+// STREAM copy of n 8-byte words: the attainable HBM rate of a plain
+// read-once write-once sweep, against which the step's rate is judged.
+__global__ __launch_bounds__(256) void k_stream_copy(const double* __restrict__ a,
+                                                     double* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+hipError_t launch_stream_copy(const double* src, double* dst, size_t n, hipStream_t s) {
+  const size_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, s, src,
+                     dst, n);
+  return hipGetLastError();
+}
+
 }  // namespace scd

@@ -85,3 +85,12 @@ def test_host_angle_formulas_match_oracle():
             p = W.params(8, 8, 8, 0.12, rho_wall=W.asymmetric_wall(d), psi=psi)
             assert scd.binding.huang_angle(p, 0.74, 0.01) == pytest.approx(
                 O.huang_angle(p, 0.74, 0.01), abs=1e-12)
+
+
+def test_stream_copy_rejects_bad_arguments():
+    """Argument checks return before any device call."""
+    lib = scd.lib()
+    assert lib.scd_stream_copy(None, None, 8, None) == B.SCD_EINVAL
+    assert lib.scd_stream_copy(4096, 8192, 12, None) == B.SCD_EINVAL      # not a multiple of 8
+    assert lib.scd_stream_copy(4100, 8192, 16, None) == B.SCD_EINVAL      # misaligned source
+    assert lib.scd_stream_copy(4096, 4104, 64, None) == B.SCD_EINVAL      # overlapping
