@@ -81,21 +81,34 @@ def timed_relaxation(scd, W, torch, dtype, steps, warmup, obs_every, tile, strea
     e1.record(stream)
     torch.cuda.synchronize()
     launch_ms = e0.elapsed_time(e1) / nsteps
+    # layout ceiling: the step's pulls and stores without its arithmetic
+    e0.record(stream)
+    for _ in range(nsteps):
+        L.pull_copy()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / nsteps
     ca = L.contact_angle(c["ca"])
     variant, zc = L.tile()
     tx, ty, zmarch, waves = scd.tile_list()[variant]
     return {"mlups": nf * nsteps / wall / 1e6, "ms_per_step": wall * 1e3 / nsteps, "steps": nsteps,
-            "launch_ms": launch_ms, "fluid_nodes": nf, "theta_e1": ca["theta_e1"],
+            "launch_ms": launch_ms, "pull_copy_ms": copy_ms, "fluid_nodes": nf,
+            "theta_e1": ca["theta_e1"],
             "theta_e2": ca["theta_e2"],
             "tile": {"tx": tx, "ty": ty, "zmarch": zmarch, "waves_per_simd": waves, "zchunk": zc}}
 
 
 def roofline(res, bytes_per_node, traffic):
     achieved = bytes_per_node * res["fluid_nodes"] / (res["launch_ms"] * 1e-3) / 1e9
+    layout = bytes_per_node * res["fluid_nodes"] / (res["pull_copy_ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_step (fused pull-stream, force, collide)",
-            "bytes_per_fluid_node": bytes_per_node, "launch_us": round(res["launch_ms"] * 1e3, 2)}
+            "bytes_per_fluid_node": bytes_per_node, "launch_us": round(res["launch_ms"] * 1e3, 2),
+            # the same pulls and stores with no arithmetic (k_pull_copy): the
+            # rate the state layout itself allows
+            "layout_copy": {"GBs": round(layout, 1), "us": round(res["pull_copy_ms"] * 1e3, 2),
+                            "step_frac": round(achieved / layout, 4)}}
 
 
 def measured_traffic():

@@ -337,6 +337,15 @@ scd_status scd_fill_state(scd_lattice* h, double value);
  * Timed by the caller, it gives the attainable HBM rate of a read-once
  * write-once sweep: the ceiling the fused step's rate is compared with. */
 scd_status scd_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+/* Measurement helper: the fused step's data movement without its
+ * arithmetic.  One launch on the handle's stream in which every fluid node
+ * pulls its 2 x 19 populations from the current state exactly as a step does
+ * (periodic neighbours, mid-grid bounce-back) and writes them unchanged to
+ * the other population buffer.  The current state is left as it is; the
+ * other buffer (the next step's destination) is overwritten.  Timed by the
+ * caller, it gives the HBM rate the state layout allows, the ceiling the
+ * step's rate is compared with.  Asynchronous. */
+scd_status scd_pull_copy(scd_lattice* h);
 
 const char* scd_last_error(void);
 const char* scd_version(void);

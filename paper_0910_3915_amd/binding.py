@@ -105,6 +105,7 @@ _PROTOS = {
     "scd_batch_graph_replay": [_VP, _I64],
     "scd_batch_autotune": [_VP, _I32, ctypes.c_char_p, ctypes.POINTER(_I32), ctypes.POINTER(_D)],
     "scd_stream_copy": [_VP, _VP, ctypes.c_size_t, _VP],
+    "scd_pull_copy": [_VP],
 }
 
 
@@ -282,6 +283,12 @@ class Lattice:
         lat = cls(d["params"], d["solid"].numpy(), device=device, adjoint=adjoint, stream=stream)
         lat.set_state(d["state"], d["step"])
         return lat
+
+    def pull_copy(self):
+        """One launch of the step's data movement without arithmetic (the
+        populations pulled as by a step, stored unchanged in the other
+        buffer); the current state is kept."""
+        check(lib().scd_pull_copy(self.h))
 
     def fill_state(self, value):
         check(lib().scd_fill_state(self.h, float(value)))

@@ -370,6 +370,13 @@ scd_status scd_fill_state(scd_lattice* h, double value) {
   return SCD_OK;
 }
 
+scd_status scd_pull_copy(scd_lattice* h) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  HIPCHK(launch_pull_copy(h->p.dtype, h->pop[h->cur], h->links(), h->pop[1 - h->cur], h->p.nx,
+                          h->p.ny, h->p.nz, h->stream));
+  return SCD_OK;
+}
+
 scd_status scd_pressure_tensor(scd_lattice* h, double* d_P) {
   if (!h || !d_P) return fail(SCD_EINVAL, "NULL argument");
   HIPCHK(launch_pressure(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz, h->ph,

@@ -595,6 +595,43 @@ __global__ __launch_bounds__(256) void k_stream_copy(const double* __restrict__ 
     b[i] = a[i];
 }
 
+// Layout ceiling: the fused step's data movement without its arithmetic.
+// Every fluid node pulls its 38 populations exactly as the step does
+// (periodic neighbours, bounce-back from the link mask) and stores them
+// unchanged at its own index of dst; wall nodes are skipped.
+template <typename real>
+__global__ __launch_bounds__(256) void k_pull_copy(const real* __restrict__ src,
+                                                   const uint32_t* __restrict__ links,
+                                                   real* __restrict__ dst, int nx, int ny,
+                                                   int nz) {
+  const int N = nx * ny * nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    if (lb & SELF_SOLID) continue;
+    int xs[3], ys[3], zs[3];
+    axis3(i % nx, nx, xs);
+    axis3((i / nx) % ny, ny, ys);
+    axis3(i / (nx * ny), nz, zs);
+    real n[38];
+    pull38(src, N, i, xs, ys, zs, nx, ny, lb, n);
+#pragma unroll
+    for (int k = 0; k < 38; ++k) dst[(size_t)k * N + i] = n[k];
+  }
+}
+
+hipError_t launch_pull_copy(int dtype, const void* src, const uint32_t* links, void* dst, int nx,
+                            int ny, int nz, hipStream_t s) {
+  const size_t N = (size_t)nx * ny * nz;
+  const unsigned g = (unsigned)((N + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_pull_copy<double>, dim3(g), dim3(256), 0, s, (const double*)src, links,
+                       (double*)dst, nx, ny, nz);
+  else
+    hipLaunchKernelGGL(k_pull_copy<float>, dim3(g), dim3(256), 0, s, (const float*)src, links,
+                       (float*)dst, nx, ny, nz);
+  return hipGetLastError();
+}
+
 hipError_t launch_stream_copy(const double* src, double* dst, size_t n, hipStream_t s) {
   const size_t g = (n + 255) / 256;
   hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)(g > 65536 ? 65536 : g)), dim3(256), 0, s, src,

@@ -19,3 +19,28 @@ def test_stream_copy_is_bitwise(n):
     scd.stream_copy(src, dst, s)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pull_copy_is_the_streaming_step(dtype):
+    """scd_pull_copy keeps the state and writes, at every fluid node of the
+    other buffer, exactly the oracle's pull-streaming (periodic neighbours,
+    bounce-back) of the state: pure copies, so bit for bit."""
+    import numpy as np
+    import oracle as O
+    import workloads as W
+    announce(f"pull copy: 20x18x14 droplet, {dtype}")
+    c = W.droplet_case(20, 18, 14, 5.0, 0.12, 0.2, dtype=dtype)
+    L = scd.Lattice(c["params"], c["solid"])
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    L.step(3)
+    before = L.get_state().clone()
+    L.pull_copy()
+    torch.cuda.synchronize()
+    assert torch.equal(L.get_state(), before)
+    other = L.pop[1] if torch.equal(L.pop[0], before) else L.pop[0]
+    Lo = O.Lattice(W.params(20, 18, 14, 0.12), c["solid"])
+    want = O.to_gpu_layout(Lo.stream(O.from_gpu_layout(before.cpu().double().numpy())))
+    got = other.cpu().double().numpy()
+    fluid = c["solid"] == 0
+    assert np.array_equal(got[:, :, fluid], want[:, :, fluid])
