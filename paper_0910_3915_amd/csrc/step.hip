@@ -142,7 +142,7 @@ __device__ __forceinline__ void collide_node(const LatDev<real>& L, const real (
 //             collided plane is pulled again (from L2 / the last-level
 //             cache): one set live, so more waves fit on a SIMD.
 constexpr int VAR_REG = 0;
-constexpr int VAR_REPULL = 1;
+[[maybe_unused]] constexpr int VAR_REPULL = 1;
 
 // One z-marching tile of the fused step (shared by the single-lattice and
 // the batched kernels).  lds: 4 * Tile::P entries.
@@ -163,14 +163,12 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   // halo positions served by this thread
   int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT];
   bool hval[T::HPT];
-  // halo positions are dealt out lane-major over all waves, so every wave
-  // pulls about the same number of halo nodes per plane (the per-plane
-  // barrier waits for the slowest wave)
-  constexpr int HW = T::HPT * T::NT / 64;  // waves that take halo slots
+  // halo positions are dealt wave-major: consecutive lanes take consecutive
+  // halo nodes, the first waves take all of them and the others issue no
+  // halo loads (no wave pulls more than HPT nodes either way)
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
-    const int slot = tid + h * T::NT;
-    int q = (slot & 63) * HW + (slot >> 6);
+    const int q = tid + h * T::NT;
     hval[h] = q < T::R;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
@@ -364,17 +362,16 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   // LDS ring: 4 planes x 2 species x P positions; plane slot s, species c
   auto ring = [&](int zr, int c) { return lds + ((zr & 3) * 2 + c) * T::P; };
 
-  // halo tasks (node position, species) dealt lane-major over the waves
-  constexpr int HW = T::HPT * T::NT / 64;
+  // halo tasks dealt wave-major as the interior: lanes 0-31 of a wave take
+  // species 0 of 32 consecutive halo nodes, lanes 32-63 species 1
   int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
   bool hval[T::HPT];
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
-    const int t = (sl & 63) * HW + (sl >> 6);
-    hval[h] = t < T::TASKS;
-    const int q = t >> 1;
-    hsp[h] = t & 1;
+    const int q = (sl >> 6) * 32 + (sl & 31);
+    hval[h] = q < T::R;
+    hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
@@ -635,16 +632,18 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
   const int pos = (ty + 1) * T::LX + (tx + 1);
   auto ring = [&](int zr, int c) { return lds + ((zr & (RS - 1)) * 2 + c) * T::P; };
 
-  constexpr int HW = T::HPT * T::NT / 64;
+  // Halo tasks are dealt wave-major, laid out like the interior: lanes 0-31
+  // of a wave take species 0 of 32 consecutive halo nodes, lanes 32-63
+  // species 1 of the same nodes.  The first waves take all of them, so the
+  // others issue no halo loads, and each half-wave reads one run of nodes.
   int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
   bool hval[T::HPT];
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
-    const int t = (sl & 63) * HW + (sl >> 6);
-    hval[h] = t < T::TASKS;
-    const int q = t >> 1;
-    hsp[h] = t & 1;
+    const int q = (sl >> 6) * 32 + (sl & 31);
+    hval[h] = q < T::R;
+    hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
@@ -863,16 +862,15 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
   const int pos = (ty + 1) * T::LX + (tx + 1);
   auto ring = [&](int zr, int c) { return lds + ((zr & 3) * 2 + c) * T::P; };
 
-  constexpr int HW = T::HPT * T::NT / 64;
+  // halo tasks dealt wave-major as in the species-split march
   int hx[T::HPT][3], hy[T::HPT][3], hpos[T::HPT], hsp[T::HPT];
   bool hval[T::HPT];
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
-    const int t = (sl & 63) * HW + (sl >> 6);
-    hval[h] = t < T::TASKS;
-    const int q = t >> 1;
-    hsp[h] = t & 1;
+    const int q = (sl >> 6) * 32 + (sl & 31);
+    hval[h] = q < T::R;
+    hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
