@@ -296,23 +296,34 @@ def copy_probe(torch, scd, stream, nbytes=1 << 30, reps=20):
 
 
 def cpu_baseline(W, seconds):
+    """The oracle on the host cores: all its threads for `seconds`, then one
+    thread for a third of that (a shorter sample of the same run)."""
     import oracle
     c = W.config_throughput(delta=0.2)
     L = oracle.Lattice(c["params"], c["solid"])
     L.init_equilibrium(c["rho_a"], c["rho_b"])
     nf = fluid_nodes(c["solid"])
-    L.step(1)  # first touch
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        L.step(1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or steps >= 1000:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def sample(limit):
+        L.step(1)  # first touch
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            L.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= limit or steps >= 1000:
+                return steps, el
+
+    cores = oracle.num_threads()
+    steps, el = sample(seconds)
+    oracle.set_threads(1)
+    steps1, el1 = sample(seconds / 3)
+    oracle.set_threads(cores)
     return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"128x128x64 droplet, FP64, {steps} steps ({el:.1f} s)"}
+            "sample": f"128x128x64 droplet, FP64, {steps} steps ({el:.1f} s)",
+            "one_core": {"value": round(nf * steps1 / el1 / 1e6, 3),
+                         "sample": f"{steps1} steps ({el1:.1f} s), 1 thread"}}
 
 
 def main():

@@ -101,6 +101,10 @@ def lib():
         L.ora_huang_angle.argtypes = [ctypes.POINTER(OraParams), ctypes.c_double, ctypes.c_double]
         L.ora_surface_tension_z.restype = ctypes.c_double
         L.ora_surface_tension_z.argtypes = [vp, dp]
+        L.ora_num_threads.restype = ctypes.c_int
+        L.ora_num_threads.argtypes = []
+        L.ora_set_threads.restype = None
+        L.ora_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -272,6 +276,16 @@ class Lattice:
         dp = np.zeros(5)
         lib().ora_adjoint_step(self._h, _dp(st), _dp(lm), _dp(dp))
         return lm, dp
+
+
+def num_threads():
+    """Host threads the oracle's per-node loops use."""
+    return lib().ora_num_threads()
+
+
+def set_threads(n):
+    """Use n host threads (results are independent of the count)."""
+    lib().ora_set_threads(int(n))
 
 
 def young_angle(gamma_sg, gamma_sl, gamma_lg):

@@ -11,6 +11,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -940,4 +941,10 @@ double ora_huang_angle(const ora_params* p, double rho_in, double rho_out) {
   double gA = p->g_wall[0] * psi_of(p->psi, p->rho_wall[1]);
   double gB = p->g_wall[1] * psi_of(p->psi, p->rho_wall[0]);
   return ora_young_angle(gB, gA, p->g_ab * (rho_in - rho_out) / 2.0);
+}
+
+int ora_num_threads(void) { return omp_get_max_threads(); }
+
+void ora_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
 }

@@ -136,6 +136,12 @@ double ora_young_angle(double gamma_sg, double gamma_sl, double gamma_lg);
    (rho_out) bulk phases; degrees, clamped. */
 double ora_huang_angle(const ora_params* p, double rho_in, double rho_out);
 
+/* Host threads of the per-node loops (OpenMP): the count in use, and a
+ * setter (n >= 1).  Results do not depend on it: reductions run in a fixed
+ * serial order. */
+int ora_num_threads(void);
+void ora_set_threads(int n);
+
 /* contact angle of the current state; returns 0, or -4 when no droplet */
 int ora_contact_angle(const ora_lattice* L, const ora_ca_cfg* cfg, ora_ca* out);
 /* same, on a given order-parameter field phi (one value per node); solid

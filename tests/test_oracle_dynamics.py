@@ -118,3 +118,21 @@ def test_demixing_threshold(ora, tau):
     # a plain mean-field threshold without the (tau - 1/2)/tau factor would
     # put both couplings deep inside the stable region
     assert 1.1 * gc < 1.0 / (15.0 * 0.74)
+
+
+def test_result_independent_of_thread_count(ora):
+    """The oracle's per-node loops run on host threads; reductions run in a
+    fixed serial order, so one thread and all threads give the same state
+    and observables bit for bit."""
+    c = W.droplet_case(20, 18, 14, 5.0, 0.12, 0.2)
+    n0 = ora.num_threads()
+    out = []
+    for n in (1, max(2, n0)):
+        ora.set_threads(n)
+        L = ora.Lattice(c["params"], c["solid"])
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(6)
+        out.append((L.get_state(), L.observables()["mass"], L.contact_angle(c["ca"])["theta_e2"]))
+    ora.set_threads(n0)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
