@@ -323,12 +323,16 @@ static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : ADJ_
 template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                             const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
-                            real* rhof, real* qf, real* df, real* ef, double* partials,
-                            int accumulate, hipStream_t s) {
+                            real* rhof, const real* rho_cached, real* qf, real* df, real* ef,
+                            double* partials, int accumulate, hipStream_t s) {
   const Phys<real> ph = phys_cast<real>(phd);
   const size_t N = (size_t)nx * ny * nz;
-  hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
-  if (e != hipSuccess) return e;
+  if (rho_cached) {
+    rhof = const_cast<real*>(rho_cached);  // read only below
+  } else {
+    hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, C,
                      lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
@@ -344,9 +348,9 @@ __global__ void k_sum5(const double* __restrict__ partials, int nblocks, double*
 
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
-                          void* rho_field, void* q_field, void* d_field, void* e_field,
-                          double* partials, double* dparams_dev, double* acc_partials,
-                          hipStream_t s) {
+                          void* rho_field, const void* rho_cached, void* q_field, void* d_field,
+                          void* e_field, double* partials, double* dparams_dev,
+                          double* acc_partials, hipStream_t s) {
   // with acc_partials the block partials accumulate over steps and are summed
   // only when read (launch_adjoint_sum); otherwise this step's sum goes to
   // dparams_dev
@@ -355,12 +359,13 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
   hipError_t e;
   if (dtype == 0)
     e = adjoint_t<double>((const double*)state_t, (const double*)lam_in, (double*)lam_out, links,
-                          nx, ny, nz, ph, (double*)rho_field, (double*)q_field, (double*)d_field,
-                          (double*)e_field, part, accumulate, s);
+                          nx, ny, nz, ph, (double*)rho_field, (const double*)rho_cached,
+                          (double*)q_field, (double*)d_field, (double*)e_field, part, accumulate,
+                          s);
   else
     e = adjoint_t<float>((const float*)state_t, (const float*)lam_in, (float*)lam_out, links, nx,
-                         ny, nz, ph, (float*)rho_field, (float*)q_field, (float*)d_field,
-                         (float*)e_field, part, accumulate, s);
+                         ny, nz, ph, (float*)rho_field, (const float*)rho_cached,
+                         (float*)q_field, (float*)d_field, (float*)e_field, part, accumulate, s);
   if (e != hipSuccess) return e;
   if (accumulate) return hipSuccess;
   return launch_adjoint_sum(dtype, partials, dparams_dev, s);

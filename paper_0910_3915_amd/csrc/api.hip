@@ -136,6 +136,8 @@ struct scd_lattice {
   int graph_cur;
   bool batch_view;  // buffers belong to a batch
   int64_t ckpt_base;  // step at which the last checkpointed forward began
+  void* rho_cache = nullptr;      // caller buffer of post-stream density fields
+  int64_t rho_cache_fields = 0;   // ... and how many 2 x N fields it holds
   uint32_t* links() const { return (uint32_t*)(work + wl.links); }
   double* wd(size_t off) const { return (double*)(work + off); }
   void* wv(size_t off) const { return (void*)(work + off); }
@@ -143,10 +145,10 @@ struct scd_lattice {
 
 namespace {
 
-// Defaults from variant sweeps on MI355X (128 x 128 x 64 droplet), both on
-// 32 x 8 tiles at two waves per SIMD: FP64 as the species-split z-march with
-// streaming stores, FP32 as the variant that issues all loads of a plane at
-// once (in FP64 that one needs 265 registers and falls to one wave).
+// Defaults from variant sweeps on MI355X (128 x 128 x 64 and larger
+// droplets): FP64 marches three planes per barrier on 32 x 4 tiles at one
+// wave per SIMD (its registers do not fit two), FP32 two planes per barrier
+// on 64 x 4 tiles at two waves per SIMD.
 int default_variant(int dtype) {
   int v = dtype == SCD_F64 ? variant_find(32, 4, 7, 1) : variant_find(64, 4, 6, 2);
   return v < 0 ? 0 : v;
@@ -512,10 +514,12 @@ scd_status scd_ca_seed(scd_lattice* h, const scd_ca_cfg* cfg, double dL_dtheta, 
 }
 
 static scd_status adjoint_enqueue(scd_lattice* h, const void* state_t, const void* lam_in,
-                                  void* lam_out, bool accumulate) {
+                                  void* lam_out, bool accumulate,
+                                  const void* rho_cached = nullptr) {
   HIPCHK(launch_adjoint(h->p.dtype, state_t, lam_in, lam_out, h->links(), h->p.nx, h->p.ny,
-                        h->p.nz, h->ph, h->wv(h->wl.rho), h->wv(h->wl.q), h->wv(h->wl.d),
-                        h->wv(h->wl.e), h->wd(h->wl.adj_partials), h->wd(h->wl.adj_dparams),
+                        h->p.nz, h->ph, h->wv(h->wl.rho), rho_cached, h->wv(h->wl.q),
+                        h->wv(h->wl.d), h->wv(h->wl.e), h->wd(h->wl.adj_partials),
+                        h->wd(h->wl.adj_dparams),
                         accumulate ? h->wd(h->wl.adj_acc) : nullptr, h->stream));
   return SCD_OK;
 }
@@ -594,20 +598,40 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // at t0) and apply the adjoint steps t1 - 1 .. t0.  Each recomputed step
 // writes its successor's slot of d_seg directly (slot j holds state
 // t0 + 1 + j), so the segment costs t1 - t0 - 1 steps and no state copies.
+// With a density cache of at least t1 - t0 - 1 fields (and a step variant
+// that writes densities), each recomputed step also stores the post-stream
+// densities of the state it reads, and the adjoint of that state uses them
+// instead of a separate density pass; the last state of the segment, which
+// no recomputed step reads, still gets its own pass.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
   const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t rbytes = 2 * h->N * real_size(h->p.dtype);
+  const bool cache = h->rho_cache && h->rho_cache_fields >= t1 - t0 - 1 &&
+                     variant_writes_density(h->variant);
   auto state = [&](int64_t t) -> const void* {
     return t == t0 ? d_start : (const char*)d_seg + (size_t)(t - t0 - 1) * bytes;
   };
+  auto rho = [&](int64_t t) -> void* {
+    return cache && t + 1 < t1 ? (char*)h->rho_cache + (size_t)(t - t0) * rbytes : nullptr;
+  };
   for (int64_t t = t0; t + 1 < t1; ++t)
     HIPCHK(launch_step(h->p.dtype, state(t), (char*)d_seg + (size_t)(t - t0) * bytes, h->links(),
-                       h->p.nx, h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream));
+                       h->p.nx, h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream,
+                       rho(t)));
   for (int64_t t = t1 - 1; t >= t0; --t) {
-    scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true);
+    scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true, rho(t));
     if (st) return st;
     *lc = 1 - *lc;
   }
+  return SCD_OK;
+}
+
+scd_status scd_ckpt_density_cache(scd_lattice* h, void* d_buf, int64_t nfields) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (nfields < 0 || (nfields > 0 && !d_buf)) return fail(SCD_EINVAL, "bad density cache");
+  h->rho_cache = nfields > 0 ? d_buf : nullptr;
+  h->rho_cache_fields = nfields;
   return SCD_OK;
 }
 

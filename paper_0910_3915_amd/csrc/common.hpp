@@ -45,6 +45,7 @@ struct LatDev {
   int nx, ny, nz;
   int N;                          // nx * ny * nz (< 2^31)
   Phys<real> ph;
+  real* __restrict__ rho_out;     // optional: post-stream densities of src, rho[a*N + i]
 };
 
 template <typename real>

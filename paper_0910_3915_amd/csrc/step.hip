@@ -701,7 +701,8 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
     for (int h = 0; h < T::HPT; ++h)
       if (!(lh[h] & SELF_SOLID)) pull19_cols<real>(hbase[h], NS, hcol[h], zo, lh[h], hm[h]);
   };
-  // densities of plane j -> e values into its ring slot
+  // densities of plane j -> e values into its ring slot (and, when asked
+  // for, the densities of the chunk's own planes to rho_out)
   auto reduce = [&](int j, uint32_t li, const uint32_t(&lh)[T::HPT], const real(&n)[19],
                     const real(&hm)[T::HPT][19]) {
     const int zr = zof(j);
@@ -712,6 +713,8 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
       for (int k = 0; k < Q; ++k) r += n[k];
     }
     ring(zr, 1 - a)[pos] = e_of(a, wall, r);
+    if (L.rho_out && j >= 1 && j <= M && active)
+      L.rho_out[(size_t)a * N + (size_t)zr * nx * ny + cidx] = r;
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
       if (!hval[h]) continue;
@@ -1276,15 +1279,21 @@ static hipError_t launch_step_t(const LatDev<real>& L, int variant, int zc, int 
 
 hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* links, int nx,
                        int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
-                       hipStream_t s) {
+                       hipStream_t s, void* rho_out) {
   if (dtype == 0) {
     LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
-                     phys_cast<double>(ph)};
+                     phys_cast<double>(ph), (double*)rho_out};
     return launch_step_t(L, variant, zc, remap, s);
   }
   LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
-                  phys_cast<float>(ph)};
+                  phys_cast<float>(ph), (float*)rho_out};
   return launch_step_t(L, variant, zc, remap, s);
+}
+
+bool variant_writes_density(int variant) {
+  if (variant < 0 || variant >= variant_count()) return false;
+  const int var = kVariants[variant][2];
+  return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD;
 }
 
 template <typename real>
@@ -1317,11 +1326,11 @@ void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_
                  int ny, int nz, const PhysD& ph) {
   if (dtype == 0) {
     LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
-                     phys_cast<double>(ph)};
+                     phys_cast<double>(ph), nullptr};
     *(LatDev<double>*)out = L;
   } else {
     LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
-                    phys_cast<float>(ph)};
+                    phys_cast<float>(ph), nullptr};
     *(LatDev<float>*)out = L;
   }
 }

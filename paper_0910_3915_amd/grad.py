@@ -21,10 +21,13 @@ class GradSetup:
     every K2 steps inside a segment (two levels), for lattices whose states
     are too large to hold K of them.  rho_a = rho_b = None starts every
     forward pass from the lattice's current state instead of re-initialising.
+    density_cache keeps the post-stream densities of each recomputed segment
+    (2 x N reals per step of a segment), which spares the adjoint its own
+    density pass; the gradient is the same bit for bit.
     """
 
     def __init__(self, params, solid, rho_a, rho_b, nsteps, ckpt_every, ca_cfg, target_deg,
-                 device="cuda", stream=None, inner=None, lattice=None):
+                 device="cuda", stream=None, inner=None, lattice=None, density_cache=True):
         self.lat = lattice or B.Lattice(params, solid, device=device, adjoint=True, stream=stream)
         self.params = dict(params)
         self.nsteps = int(nsteps)
@@ -45,6 +48,13 @@ class GradSetup:
         else:
             self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
         self.lam = torch.empty((2,) + shape, dtype=dt, device=dev)
+        seg_len = self.K2 or self.K
+        self.rho_cache = None
+        if density_cache and seg_len > 1:
+            self.rho_cache = torch.empty((seg_len - 1, 2) + self.lat.shape, dtype=dt, device=dev)
+        B.check(B.lib().scd_ckpt_density_cache(
+            self.lat.h, None if self.rho_cache is None else B._ptr(self.rho_cache),
+            0 if self.rho_cache is None else seg_len - 1))
         self.theta = float("nan")
         self.start = None if rho_a is not None else self.lat.get_state()
 

@@ -121,3 +121,29 @@ def test_gradient_from_current_state_matches_oracle():
         lam, dp = Lo.adjoint_step(states[t], lam)
         go += dp
     assert np.allclose(g, go, rtol=1e-8, atol=0), (g, go)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("inner", [None, 4])
+def test_density_cache_gives_the_same_gradient(dtype, inner):
+    """The densities a recomputed step writes are those the adjoint's own
+    density pass computes (same pulls, same summation order), so the cached
+    sweep reproduces the plain one bit for bit; a variant that writes no
+    densities falls back to the density pass."""
+    announce(f"density cache: {dtype}, inner {inner}")
+    c = _tiny(0.1)
+    c["params"] = dict(c["params"], dtype=dtype)
+    nsteps, K, target = 40, 9, 115.0
+    out = []
+    for cache in (False, True):
+        s = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
+                          inner=inner, density_cache=cache)
+        out.append((s.forward(), s.backward()))
+    assert out[0] == out[1]
+    reg = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
+                        inner=inner, density_cache=True)
+    reg.lat.set_tile(scd.variant_index(64, 4, 0, 1), 4)
+    ref = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
+                        inner=inner, density_cache=False)
+    ref.lat.set_tile(scd.variant_index(64, 4, 0, 1), 4)
+    assert (reg.forward(), reg.backward()) == (ref.forward(), ref.backward())
