@@ -288,8 +288,10 @@ scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_
 scd_status scd_tile_list(int32_t* h_rows, int32_t cap, int32_t* n);
 scd_status scd_tile_set(scd_lattice* h, int32_t variant, int32_t zc);
 scd_status scd_tile_get(const scd_lattice* h, int32_t* variant, int32_t* zc);
-/* Time every compiled variant with several z-chunks on this lattice and
- * keep the fastest: h_best[2] = variant, zc; *h_ms = its time per step.  The
+/* Time every compiled variant with several z-chunks (4, 8, ..., 128 and the
+ * chunk the default wave-count model picks for that variant) on this
+ * lattice and keep the fastest: h_best[2] = variant, zc; *h_ms = its time
+ * per step.  The
  * trial steps advance (and overwrite) the lattice state: re-initialise it
  * afterwards.  cache_path (may be NULL): JSON-lines file of earlier results
  * keyed by dims, dtype, device and variant count; a hit skips the trials. */

@@ -830,13 +830,16 @@ scd_status scd_autotune(scd_lattice* h, int32_t steps_per_trial, const char* cac
   HIPCHK(hipEventCreate(&e1));
   double bms = 1e30;
   int b[2] = {h->variant, h->zc};
-  const int zcs[] = {4, 8, 16, 32, 64, 128};
   for (int i = 0; i < variant_count(); ++i) {
     int tx, ty, var, wpe;
     variant_at(i, &tx, &ty, &var, &wpe);
     if (tx > 2 * h->p.nx && tx > 16) continue;  // mostly idle lanes
-    for (int zc : zcs) {
+    // powers of two and the chunk the wave-count model picks for this variant
+    const int zcs[] = {4, 8, 16, 32, 64, 128, default_zc(h->p, i)};
+    for (int zi = 0; zi < 7; ++zi) {
+      const int zc = zcs[zi];
       if (zc > h->p.nz && zc != zcs[0]) continue;
+      if (zi == 6 && (zc & (zc - 1)) == 0 && zc <= 128) continue;  // already timed
       scd_status st = scd_tile_set(h, i, zc);
       if (st) return st;
       st = enqueue_steps(h, 1);  // warm-up
