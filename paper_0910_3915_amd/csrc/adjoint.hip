@@ -3,15 +3,16 @@
 //
 // Given the state C^t and lambda' = dL/dC^{t+1}, one reverse step produces
 // lambda = dL/dC^t and the gradient with respect to the wall contents, the
-// fluid coupling and the wall couplings.  Three passes over the lattice:
+// fluid coupling and the wall couplings.  Two passes over the lattice (three
+// in FP32), after the post-stream densities of C^t (computed or cached):
 //   1. per fluid node: recompute the forward quantities (pull, moments, psi,
 //      force from the neighbours' post-stream densities, velocities) and
 //      transpose the collision (Eq. Equil), the velocity shift and the local
 //      part of the force; store q^a = psi^a dL/dF^a, D^a = dL/drho^a and
 //      E^a = dL/dj^a, and accumulate the parameter gradient;
-//   2. per fluid node: add the transposed force stencil, i.e. the gather
-//      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) into D;
-//   3. per node: transposed streaming with bounce-back, as a push of
+//   2. per node: add the transposed force stencil, i.e. the gather
+//      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) to D (FP32: as
+//      a pass of its own), then stream transposed with bounce-back, as a push of
 //      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k to x - c_k (or to the
 //      node itself on the opposite velocity next to a wall).
 #include "common.hpp"
@@ -230,7 +231,31 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
           accumulate ? partials[blockIdx.x * RED_STRIDE + c] + gp[c] : gp[c];
 }
 
-// D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b
+// D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b:
+// the transposed force stencil as a pass of its own (the FP32 path; the FP64
+// path does it inside the push-stream pass)
+template <typename real>
+__device__ __forceinline__ void stencil_acc(const real* __restrict__ qf, int N,
+                                            const int (&xs)[3], const int (&ys)[3],
+                                            const int (&zs)[3], int nx, int ny,
+                                            const Phys<real>& ph, real (&acc)[2]) {
+  acc[0] = acc[1] = 0;  // acc[b] from q of the other species
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    const int x = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      // only the components along which c_k moves (60 of the 108 loads)
+      real qc = 0;
+      if (CX[k]) qc += qf[(size_t)(a * 3 + 0) * N + x] * CX[k];
+      if (CY[k]) qc += qf[(size_t)(a * 3 + 1) * N + x] * CY[k];
+      if (CZ[k]) qc += qf[(size_t)(a * 3 + 2) * N + x] * CZ[k];
+      acc[1 - a] += w * qc;
+    }
+  }
+}
+
 template <typename real>
 __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict__ links,
                                                      const real* __restrict__ rhof, int nx, int ny,
@@ -244,38 +269,30 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
-    real acc[2] = {0, 0};  // acc[b] from q of the other species
-#pragma unroll
-    for (int k = 1; k < Q; ++k) {
-      const int x = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
-      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        // only the components along which c_k moves (60 of the 108 loads)
-        real qc = 0;
-        if (CX[k]) qc += qf[(size_t)(a * 3 + 0) * N + x] * CX[k];
-        if (CY[k]) qc += qf[(size_t)(a * 3 + 1) * N + x] * CY[k];
-        if (CZ[k]) qc += qf[(size_t)(a * 3 + 2) * N + x] * CZ[k];
-        acc[1 - a] += w * qc;
-      }
-    }
+    real acc[2];
+    stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
       df[(size_t)b * N + i] += dpsi_of(ph.psi_form, rhof[(size_t)b * N + i]) * (-ph.gab * acc[b]);
   }
 }
 
-// Transposed streaming, as a push from every fluid node y:
-//   mu_k(y) = D(y) + E(y) . c_k + (1 - 1/tau) lambda'_k(y)   (= dL/dn_k(y))
-// goes to lambda_k(y - c_k) when y - c_k is fluid (the forward step pulled
-// n_k(y) from C_k(y - c_k)), and mu_{opp k}(y) goes to lambda_k(y) itself
-// when y + c_k is a wall (the forward step bounced C_k(y) back into
-// n_{opp k}(y)).  Every entry of lambda is written exactly once, and all
-// loads are of the node's own values.
-template <typename real>
+// Transposed streaming (FUSED: with the transposed force stencil in the same
+// pass).  First, when FUSED, the non-local part of dL/drho at fluid node y,
+// from q of the other species at the 18 upstream nodes:
+//   D^a(y) = D_local^a(y) + psi'(rho^a(y)) * (-g_ab sum_k W_k q^b(y - c_k) . c_k)
+// (only the components along which c_k moves are loaded: 60 loads).  Then
+// the push: mu_k(y) = D(y) + E(y) . c_k + (1 - 1/tau) lambda'_k(y)
+// (= dL/dn_k(y)) goes to lambda_k(y - c_k) when y - c_k is fluid (the
+// forward step pulled n_k(y) from C_k(y - c_k)), and mu_{opp k}(y) goes to
+// lambda_k(y) itself when y + c_k is a wall (the forward step bounced C_k(y)
+// back into n_{opp k}(y)).  Every entry of lambda is written exactly once.
+template <typename real, bool FUSED>
 __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__ links, int nx,
                                                     int ny, int nz, Phys<real> ph,
                                                     const real* __restrict__ lam,
+                                                    const real* __restrict__ rhof,
+                                                    const real* __restrict__ qf,
                                                     const real* __restrict__ df,
                                                     const real* __restrict__ ef,
                                                     real* __restrict__ out) {
@@ -291,9 +308,12 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
+    real acc[2] = {0, 0};
+    if constexpr (FUSED) stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const real D = df[(size_t)a * N + i];
+      real D = df[(size_t)a * N + i];
+      if constexpr (FUSED) D += dpsi_of(ph.psi_form, rhof[(size_t)a * N + i]) * (-ph.gab * acc[a]);
       const real Ex = ef[(size_t)(a * 3 + 0) * N + i];
       const real Ey = ef[(size_t)(a * 3 + 1) * N + i];
       const real Ez = ef[(size_t)(a * 3 + 2) * N + i];
@@ -336,10 +356,14 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
   hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, C,
                      lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
-  hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny, nz,
-                     ph, qf, df);
-  hipLaunchKernelGGL(k_adj_stream<real>, dim3(blocks), dim3(256), 0, s, links, nx, ny, nz, ph,
-                     lam_in, df, ef, lam_out);
+  // FP64 adds the transposed stencil inside the push pass (one fewer sweep
+  // of D); in FP32 the gathers slow that pass more than the sweep costs
+  constexpr bool FUSED = sizeof(real) == 8;
+  if (!FUSED)
+    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny,
+                       nz, ph, qf, df);
+  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(blocks), dim3(256), 0, s, links, nx, ny,
+                     nz, ph, lam_in, rhof, qf, df, ef, lam_out);
   return hipGetLastError();
 }
 
