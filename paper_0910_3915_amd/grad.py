@@ -52,9 +52,6 @@ class GradSetup:
         self.rho_cache = None
         if density_cache and seg_len > 1:
             self.rho_cache = torch.empty((seg_len - 1, 2) + self.lat.shape, dtype=dt, device=dev)
-        B.check(B.lib().scd_ckpt_density_cache(
-            self.lat.h, None if self.rho_cache is None else B._ptr(self.rho_cache),
-            0 if self.rho_cache is None else seg_len - 1))
         self.theta = float("nan")
         self.start = None if rho_a is not None else self.lat.get_state()
 
@@ -80,6 +77,19 @@ class GradSetup:
 
     def backward(self):
         g = (ctypes.c_double * 5)()
+        # the cache is registered for this sweep only, so the lattice never
+        # keeps a pointer to a buffer this object may outlive
+        if self.rho_cache is not None:
+            B.check(B.lib().scd_ckpt_density_cache(self.lat.h, B._ptr(self.rho_cache),
+                                                   self.rho_cache.shape[0]))
+        try:
+            self._sweep(g)
+        finally:
+            if self.rho_cache is not None:
+                B.check(B.lib().scd_ckpt_density_cache(self.lat.h, None, 0))
+        return list(g)
+
+    def _sweep(self, g):
         if self.K2:
             B.check(B.lib().scd_ckpt_backward2(self.lat.h, self.nsteps, self.K, self.K2, B._ptr(self.ckpt),
                                                B._ptr(self.mid), B._ptr(self.seg), B._ptr(self.lam),
@@ -88,7 +98,6 @@ class GradSetup:
             B.check(B.lib().scd_ckpt_backward(self.lat.h, self.nsteps, self.K, B._ptr(self.ckpt),
                                               B._ptr(self.seg), B._ptr(self.lam), ctypes.byref(self.cfg),
                                               self.target, g))
-        return list(g)
 
 
 class ContactAngleFn(torch.autograd.Function):
