@@ -256,15 +256,17 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
 scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
                             int64_t nsteps, int64_t ckpt_every, void* d_ckpt,
                             const scd_ca_cfg* cfg, double target_deg, double* h_out);
-/* Optional density cache for the backward sweeps: d_buf holds nfields
- * fields of 2 x N reals (the lattice dtype; caller-owned, kept alive while
- * registered; nfields = 0 unregisters).  When nfields covers a recomputed
- * segment (ckpt_every - 1 fields, or K2 - 1 with two levels) and the step
- * variant is a multi-plane march (6, 7 or 8), each recomputed step also
- * writes the post-stream densities of the state it reads, and the adjoint
- * of that state reads them instead of running its own density pass.  The
+/* Optional moment cache for the backward sweeps: d_buf holds nsteps blocks
+ * of 8 x N reals (the lattice dtype: rho^A, rho^B, j^A (x, y, z), j^B (x, y,
+ * z); caller-owned, kept alive while registered; nsteps = 0 unregisters).
+ * When nsteps covers a recomputed segment (ckpt_every - 1 steps, or K2 - 1
+ * with two levels) and the step variant is a multi-plane march (6, 7 or 8),
+ * each recomputed step also writes the densities and momenta of the
+ * post-stream populations of the state it reads, and the adjoint of that
+ * state uses them instead of running a density pass and pulling the
+ * populations again.  These are the same sums in the same order, so the
  * gradient is the same bit for bit. */
-scd_status scd_ckpt_density_cache(scd_lattice* h, void* d_buf, int64_t nfields);
+scd_status scd_ckpt_moment_cache(scd_lattice* h, void* d_buf, int64_t nsteps);
 scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t ckpt_every,
                              const void* d_ckpt, void* d_seg, void* d_lam,
                              const scd_ca_cfg* cfg, double target_deg, double* h_grad);

@@ -85,7 +85,7 @@ _PROTOS = {
     "scd_adjoint_reset": [_VP],
     "scd_adjoint_read": [_VP, ctypes.POINTER(_D)],
     "scd_ckpt_forward": [_VP, _VP, _VP, _I64, _I64, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
-    "scd_ckpt_density_cache": [_VP, _VP, _I64],
+    "scd_ckpt_moment_cache": [_VP, _VP, _I64],
     "scd_ckpt_backward": [_VP, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
     "scd_ckpt_backward2": [_VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D,
                            ctypes.POINTER(_D)],

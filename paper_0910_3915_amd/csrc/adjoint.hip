@@ -54,8 +54,12 @@ __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
     }
 }
 
-template <typename real>
+// CACHED: rho and j come from mom (the moments a recomputed forward step
+// stored: rho^A, rho^B, j^A, j^B as 8 fields of N, the same sums as below)
+// and no population is pulled; rhof is then mom's first two fields.
+template <typename real, bool CACHED>
 __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
+                                                   const real* __restrict__ mom,
                                                    const real* __restrict__ lam,
                                                    const uint32_t* __restrict__ links,
                                                    const real* __restrict__ rhof, int nx, int ny,
@@ -70,7 +74,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
   // latency: the next node's populations are requested once this node's
   // neighbour densities are in, and arrive while its lambda' is read and
   // its collision transposed.
-  constexpr bool PREFETCH = sizeof(real) == 8;
+  constexpr bool PREFETCH = sizeof(real) == 8 && !CACHED;
   auto fetch = [&](int node, uint32_t& l, real(&c)[38]) {
     l = links[node];
     if (!(l & SELF_SOLID)) {
@@ -100,19 +104,24 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
-    if (!PREFETCH) pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
     real rho[2], j[2][3];
-    moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
-    moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
+    if constexpr (CACHED) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        rho[a] = mom[(size_t)a * N + i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) j[a][d] = mom[(size_t)(2 + 3 * a + d) * N + i];
+      }
+    } else {
+      if (!PREFETCH) pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
+      moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
+      moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
+    }
     real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
-    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k.
-    // For the parameter gradient the FP32 kernel keeps psi at every
-    // neighbour; the FP64 kernel, short of registers, keeps the sums
-    // T^b = sum over fluid neighbours of W_k psi^b(y) c_k (the g_ab part of
-    // S) and V = sum over wall neighbours of W_k c_k (the wall part).
+    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k;
+    // psi at every neighbour is kept for the parameter gradient
     real S[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    real T[2][3] = {{0, 0, 0}, {0, 0, 0}}, V[3] = {0, 0, 0};
-    real pnb[PREFETCH ? 1 : Q][2];
+    real pnb[Q][2];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const bool wall = (lb >> k) & 1u;
@@ -130,16 +139,8 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       const real eB = w * (wall ? ph.gw[1] : ph.gab) * pA;
       S[0][0] += CX[k] * eA; S[0][1] += CY[k] * eA; S[0][2] += CZ[k] * eA;
       S[1][0] += CX[k] * eB; S[1][1] += CY[k] * eB; S[1][2] += CZ[k] * eB;
-      if constexpr (PREFETCH) {
-        const real wA = wall ? real(0) : w * pA, wB = wall ? real(0) : w * pB;
-        const real ww = wall ? w : real(0);
-        if (CX[k]) { T[0][0] += CX[k] * wA; T[1][0] += CX[k] * wB; V[0] += CX[k] * ww; }
-        if (CY[k]) { T[0][1] += CY[k] * wA; T[1][1] += CY[k] * wB; V[1] += CY[k] * ww; }
-        if (CZ[k]) { T[0][2] += CZ[k] * wA; T[1][2] += CZ[k] * wB; V[2] += CZ[k] * ww; }
-      } else {
-        pnb[k][0] = pA;
-        pnb[k][1] = pB;
-      }
+      pnb[k][0] = pA;
+      pnb[k][1] = pB;
     }
     if (PREFETCH && i + stride < N) fetch(i + stride, lnext, n);
     real F[2][3];
@@ -197,28 +198,16 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       const real dpsi_self = -(dF[a][0] * S[a][0] + dF[a][1] * S[a][1] + dF[a][2] * S[a][2]);
       for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi[a] * dF[a][d];
       df[(size_t)a * N + i] = drho[a] + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
-      if constexpr (PREFETCH) {
-        // F^a = -psi^a S^a with S^a = g_ab T^b + g_wall^a psi_wall^b V
-        const double m = -(double)psi[a];
-        const double dTF = m * ((double)dF[a][0] * T[b][0] + (double)dF[a][1] * T[b][1] +
-                                (double)dF[a][2] * T[b][2]);
-        const double dV = m * ((double)dF[a][0] * V[0] + (double)dF[a][1] * V[1] +
-                               (double)dF[a][2] * V[2]);
-        gp[2] += dTF;
-        gp[3 + a] += (double)ph.psiw[b] * dV;
-        gp[b] += (double)ph.gw[a] * dV * (double)ph.dpsiw[b];
-      } else {
 #pragma unroll
-        for (int k = 1; k < Q; ++k) {
-          const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-          const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
-          const double t = (double)(-psi[a] * w * dFc);
-          if ((lb >> k) & 1u) {
-            gp[3 + a] += (double)ph.psiw[b] * t;
-            gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
-          } else {
-            gp[2] += (double)pnb[k][b] * t;
-          }
+      for (int k = 1; k < Q; ++k) {
+        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
+        const double t = (double)(-psi[a] * w * dFc);
+        if ((lb >> k) & 1u) {
+          gp[3 + a] += (double)ph.psiw[b] * t;
+          gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
+        } else {
+          gp[2] += (double)pnb[k][b] * t;
         }
       }
     }
@@ -343,18 +332,22 @@ static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : ADJ_
 template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                             const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
-                            real* rhof, const real* rho_cached, real* qf, real* df, real* ef,
+                            real* rhof, const real* mom, real* qf, real* df, real* ef,
                             double* partials, int accumulate, hipStream_t s) {
   const Phys<real> ph = phys_cast<real>(phd);
   const size_t N = (size_t)nx * ny * nz;
-  if (rho_cached) {
-    rhof = const_cast<real*>(rho_cached);  // read only below
+  if (mom) {
+    rhof = const_cast<real*>(mom);  // its density fields, read only below
+    hipLaunchKernelGGL((k_adj_local<real, true>), dim3(adj_local_grid(sizeof(real))),
+                       dim3(256), 0, s, C, mom, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef,
+                       partials, accumulate);
   } else {
     hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adj_local<real, false>), dim3(adj_local_grid(sizeof(real))),
+                       dim3(256), 0, s, C, mom, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef,
+                       partials, accumulate);
   }
-  hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, C,
-                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   // FP64 adds the transposed stencil inside the push pass (one fewer sweep
   // of D); in FP32 the gathers slow that pass more than the sweep costs
@@ -372,7 +365,7 @@ __global__ void k_sum5(const double* __restrict__ partials, int nblocks, double*
 
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
-                          void* rho_field, const void* rho_cached, void* q_field, void* d_field,
+                          void* rho_field, const void* mom_cached, void* q_field, void* d_field,
                           void* e_field, double* partials, double* dparams_dev,
                           double* acc_partials, hipStream_t s) {
   // with acc_partials the block partials accumulate over steps and are summed
@@ -383,12 +376,12 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
   hipError_t e;
   if (dtype == 0)
     e = adjoint_t<double>((const double*)state_t, (const double*)lam_in, (double*)lam_out, links,
-                          nx, ny, nz, ph, (double*)rho_field, (const double*)rho_cached,
+                          nx, ny, nz, ph, (double*)rho_field, (const double*)mom_cached,
                           (double*)q_field, (double*)d_field, (double*)e_field, part, accumulate,
                           s);
   else
     e = adjoint_t<float>((const float*)state_t, (const float*)lam_in, (float*)lam_out, links, nx,
-                         ny, nz, ph, (float*)rho_field, (const float*)rho_cached,
+                         ny, nz, ph, (float*)rho_field, (const float*)mom_cached,
                          (float*)q_field, (float*)d_field, (float*)e_field, part, accumulate, s);
   if (e != hipSuccess) return e;
   if (accumulate) return hipSuccess;

@@ -136,8 +136,8 @@ struct scd_lattice {
   int graph_cur;
   bool batch_view;  // buffers belong to a batch
   int64_t ckpt_base;  // step at which the last checkpointed forward began
-  void* rho_cache = nullptr;      // caller buffer of post-stream density fields
-  int64_t rho_cache_fields = 0;   // ... and how many 2 x N fields it holds
+  void* mom_cache = nullptr;      // caller buffer of moment fields of recomputed steps
+  int64_t mom_cache_steps = 0;    // ... and how many steps (8 x N reals each) it holds
   uint32_t* links() const { return (uint32_t*)(work + wl.links); }
   double* wd(size_t off) const { return (double*)(work + off); }
   void* wv(size_t off) const { return (void*)(work + off); }
@@ -515,9 +515,9 @@ scd_status scd_ca_seed(scd_lattice* h, const scd_ca_cfg* cfg, double dL_dtheta, 
 
 static scd_status adjoint_enqueue(scd_lattice* h, const void* state_t, const void* lam_in,
                                   void* lam_out, bool accumulate,
-                                  const void* rho_cached = nullptr) {
+                                  const void* mom_cached = nullptr) {
   HIPCHK(launch_adjoint(h->p.dtype, state_t, lam_in, lam_out, h->links(), h->p.nx, h->p.ny,
-                        h->p.nz, h->ph, h->wv(h->wl.rho), rho_cached, h->wv(h->wl.q),
+                        h->p.nz, h->ph, h->wv(h->wl.rho), mom_cached, h->wv(h->wl.q),
                         h->wv(h->wl.d), h->wv(h->wl.e), h->wd(h->wl.adj_partials),
                         h->wd(h->wl.adj_dparams),
                         accumulate ? h->wd(h->wl.adj_acc) : nullptr, h->stream));
@@ -598,40 +598,41 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // at t0) and apply the adjoint steps t1 - 1 .. t0.  Each recomputed step
 // writes its successor's slot of d_seg directly (slot j holds state
 // t0 + 1 + j), so the segment costs t1 - t0 - 1 steps and no state copies.
-// With a density cache of at least t1 - t0 - 1 fields (and a step variant
-// that writes densities), each recomputed step also stores the post-stream
-// densities of the state it reads, and the adjoint of that state uses them
-// instead of a separate density pass; the last state of the segment, which
-// no recomputed step reads, still gets its own pass.
+// With a moment cache of at least t1 - t0 - 1 steps (and a step variant
+// that writes moments), each recomputed step also stores the densities and
+// momenta of the post-stream populations of the state it reads, and the
+// adjoint of that state reads them instead of running a density pass and
+// pulling the populations again; the last state of the segment, which no
+// recomputed step reads, still takes the full path.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
   const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
-  const size_t rbytes = 2 * h->N * real_size(h->p.dtype);
-  const bool cache = h->rho_cache && h->rho_cache_fields >= t1 - t0 - 1 &&
-                     variant_writes_density(h->variant);
+  const size_t mbytes = 8 * h->N * real_size(h->p.dtype);
+  const bool cache = h->mom_cache && h->mom_cache_steps >= t1 - t0 - 1 &&
+                     variant_writes_moments(h->variant);
   auto state = [&](int64_t t) -> const void* {
     return t == t0 ? d_start : (const char*)d_seg + (size_t)(t - t0 - 1) * bytes;
   };
-  auto rho = [&](int64_t t) -> void* {
-    return cache && t + 1 < t1 ? (char*)h->rho_cache + (size_t)(t - t0) * rbytes : nullptr;
+  auto mom = [&](int64_t t) -> void* {
+    return cache && t + 1 < t1 ? (char*)h->mom_cache + (size_t)(t - t0) * mbytes : nullptr;
   };
   for (int64_t t = t0; t + 1 < t1; ++t)
     HIPCHK(launch_step(h->p.dtype, state(t), (char*)d_seg + (size_t)(t - t0) * bytes, h->links(),
                        h->p.nx, h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream,
-                       rho(t)));
+                       mom(t)));
   for (int64_t t = t1 - 1; t >= t0; --t) {
-    scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true, rho(t));
+    scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true, mom(t));
     if (st) return st;
     *lc = 1 - *lc;
   }
   return SCD_OK;
 }
 
-scd_status scd_ckpt_density_cache(scd_lattice* h, void* d_buf, int64_t nfields) {
+scd_status scd_ckpt_moment_cache(scd_lattice* h, void* d_buf, int64_t nsteps) {
   if (!h) return fail(SCD_EINVAL, "NULL handle");
-  if (nfields < 0 || (nfields > 0 && !d_buf)) return fail(SCD_EINVAL, "bad density cache");
-  h->rho_cache = nfields > 0 ? d_buf : nullptr;
-  h->rho_cache_fields = nfields;
+  if (nsteps < 0 || (nsteps > 0 && !d_buf)) return fail(SCD_EINVAL, "bad moment cache");
+  h->mom_cache = nsteps > 0 ? d_buf : nullptr;
+  h->mom_cache_steps = nsteps;
   return SCD_OK;
 }
 

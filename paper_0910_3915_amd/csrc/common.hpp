@@ -45,7 +45,9 @@ struct LatDev {
   int nx, ny, nz;
   int N;                          // nx * ny * nz (< 2^31)
   Phys<real> ph;
-  real* __restrict__ rho_out;     // optional: post-stream densities of src, rho[a*N + i]
+  // optional: the moments of the post-stream populations of src, as 8 fields
+  // of N: rho^A, rho^B, j^A (x, y, z), j^B (x, y, z)
+  real* __restrict__ mom_out;
 };
 
 template <typename real>

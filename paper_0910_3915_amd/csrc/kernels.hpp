@@ -38,12 +38,14 @@ hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, dou
 hipError_t launch_stream_density(int dtype, const void* pop, const uint32_t* links, void* rho,
                                  int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s);
-// rho_out (optional): the post-stream densities of src (2 x N, 0 at walls),
-// written by the variants for which variant_writes_density holds.
+// mom_out (optional): the moments of the post-stream populations of src, 8
+// fields of N (rho^A, rho^B, then j^A and j^B by component; rho is 0 at
+// walls, j is left unwritten there), written by the variants for which
+// variant_writes_moments holds.
 hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* links, int nx,
                        int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
-                       hipStream_t s, void* rho_out = nullptr);
-bool variant_writes_density(int variant);
+                       hipStream_t s, void* mom_out = nullptr);
+bool variant_writes_moments(int variant);
 hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
                              int variant, hipStream_t s);
 size_t latdev_size(int dtype);
@@ -82,15 +84,17 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
 
 // adjoint.hip
 constexpr int ADJ_BLOCKS = 2048;
-// One reverse step.  rho_cached (or nullptr): the post-stream densities of
-// state_t computed earlier (by the step that read state_t); otherwise they
-// are computed into rho_field.  acc_partials == nullptr: this step's parameter gradient
+// One reverse step.  mom_cached (or nullptr): the moments of the post-stream
+// populations of state_t in the layout of launch_step's mom_out, written
+// earlier by the step that read state_t; the local pass then takes rho and j
+// from them and pulls no populations.  Otherwise the densities are computed
+// into rho_field and the moments from the pulled populations.  acc_partials == nullptr: this step's parameter gradient
 // is summed into dparams_dev[0..5).  Otherwise the per-workgroup partials
 // accumulate in acc_partials (ADJ_BLOCKS x RED_STRIDE doubles, zeroed by the
 // caller) and launch_adjoint_sum reduces them when they are read.
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
-                          void* rho_field, const void* rho_cached, void* q_field, void* d_field,
+                          void* rho_field, const void* mom_cached, void* q_field, void* d_field,
                           void* e_field, double* partials, double* dparams_dev,
                           double* acc_partials, hipStream_t s);
 hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s);

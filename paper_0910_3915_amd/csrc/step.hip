@@ -702,7 +702,7 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
       if (!(lh[h] & SELF_SOLID)) pull19_cols<real>(hbase[h], NS, hcol[h], zo, lh[h], hm[h]);
   };
   // densities of plane j -> e values into its ring slot (and, when asked
-  // for, the densities of the chunk's own planes to rho_out)
+  // for, the densities of the chunk's own planes to mom_out)
   auto reduce = [&](int j, uint32_t li, const uint32_t(&lh)[T::HPT], const real(&n)[19],
                     const real(&hm)[T::HPT][19]) {
     const int zr = zof(j);
@@ -713,8 +713,8 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
       for (int k = 0; k < Q; ++k) r += n[k];
     }
     ring(zr, 1 - a)[pos] = e_of(a, wall, r);
-    if (L.rho_out && j >= 1 && j <= M && active)
-      L.rho_out[(size_t)a * N + (size_t)zr * nx * ny + cidx] = r;
+    if (L.mom_out && j >= 1 && j <= M && active)
+      L.mom_out[(size_t)a * N + (size_t)zr * nx * ny + cidx] = r;
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
       if (!hval[h]) continue;
@@ -736,6 +736,12 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
     const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
     const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
     if (!active || solid) return;
+    if (L.mom_out) {
+      real* m = L.mom_out + (size_t)(2 + 3 * a) * N + (size_t)zc * nx * ny + cidx;
+      m[0] = jx;
+      m[N] = jy;
+      m[2 * (size_t)N] = jz;
+    }
     // Eq. (SCforce) on species a: S^a = sum_k W_k e^a(x + c_k) c_k
     const real* sm = ring(zc - 1, a);
     const real* s0 = ring(zc, a);
@@ -1279,18 +1285,18 @@ static hipError_t launch_step_t(const LatDev<real>& L, int variant, int zc, int 
 
 hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* links, int nx,
                        int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
-                       hipStream_t s, void* rho_out) {
+                       hipStream_t s, void* mom_out) {
   if (dtype == 0) {
     LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
-                     phys_cast<double>(ph), (double*)rho_out};
+                     phys_cast<double>(ph), (double*)mom_out};
     return launch_step_t(L, variant, zc, remap, s);
   }
   LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
-                  phys_cast<float>(ph), (float*)rho_out};
+                  phys_cast<float>(ph), (float*)mom_out};
   return launch_step_t(L, variant, zc, remap, s);
 }
 
-bool variant_writes_density(int variant) {
+bool variant_writes_moments(int variant) {
   if (variant < 0 || variant >= variant_count()) return false;
   const int var = kVariants[variant][2];
   return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD;

@@ -21,13 +21,14 @@ class GradSetup:
     every K2 steps inside a segment (two levels), for lattices whose states
     are too large to hold K of them.  rho_a = rho_b = None starts every
     forward pass from the lattice's current state instead of re-initialising.
-    density_cache keeps the post-stream densities of each recomputed segment
-    (2 x N reals per step of a segment), which spares the adjoint its own
-    density pass; the gradient is the same bit for bit.
+    moment_cache keeps the densities and momenta of the post-stream
+    populations of each recomputed segment (8 x N reals per step of a
+    segment), which spares the adjoint its density pass and its pull of the
+    populations; the gradient is the same bit for bit.
     """
 
     def __init__(self, params, solid, rho_a, rho_b, nsteps, ckpt_every, ca_cfg, target_deg,
-                 device="cuda", stream=None, inner=None, lattice=None, density_cache=True):
+                 device="cuda", stream=None, inner=None, lattice=None, moment_cache=True):
         self.lat = lattice or B.Lattice(params, solid, device=device, adjoint=True, stream=stream)
         self.params = dict(params)
         self.nsteps = int(nsteps)
@@ -49,9 +50,9 @@ class GradSetup:
             self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
         self.lam = torch.empty((2,) + shape, dtype=dt, device=dev)
         seg_len = self.K2 or self.K
-        self.rho_cache = None
-        if density_cache and seg_len > 1:
-            self.rho_cache = torch.empty((seg_len - 1, 2) + self.lat.shape, dtype=dt, device=dev)
+        self.mom_cache = None
+        if moment_cache and seg_len > 1:
+            self.mom_cache = torch.empty((seg_len - 1, 8) + self.lat.shape, dtype=dt, device=dev)
         self.theta = float("nan")
         self.start = None if rho_a is not None else self.lat.get_state()
 
@@ -79,14 +80,14 @@ class GradSetup:
         g = (ctypes.c_double * 5)()
         # the cache is registered for this sweep only, so the lattice never
         # keeps a pointer to a buffer this object may outlive
-        if self.rho_cache is not None:
-            B.check(B.lib().scd_ckpt_density_cache(self.lat.h, B._ptr(self.rho_cache),
-                                                   self.rho_cache.shape[0]))
+        if self.mom_cache is not None:
+            B.check(B.lib().scd_ckpt_moment_cache(self.lat.h, B._ptr(self.mom_cache),
+                                                  self.mom_cache.shape[0]))
         try:
             self._sweep(g)
         finally:
-            if self.rho_cache is not None:
-                B.check(B.lib().scd_ckpt_density_cache(self.lat.h, None, 0))
+            if self.mom_cache is not None:
+                B.check(B.lib().scd_ckpt_moment_cache(self.lat.h, None, 0))
         return list(g)
 
     def _sweep(self, g):

@@ -96,7 +96,7 @@ def test_stream_copy_rejects_bad_arguments():
     assert lib.scd_stream_copy(4096, 4104, 64, None) == B.SCD_EINVAL      # overlapping
 
 
-def test_density_cache_rejects_bad_arguments():
+def test_moment_cache_rejects_bad_arguments():
     lib = scd.lib()
-    assert lib.scd_ckpt_density_cache(None, None, 0) == B.SCD_EINVAL
+    assert lib.scd_ckpt_moment_cache(None, None, 0) == B.SCD_EINVAL
     assert lib.scd_pull_copy(None) == B.SCD_EINVAL

@@ -125,25 +125,25 @@ def test_gradient_from_current_state_matches_oracle():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("inner", [None, 4])
-def test_density_cache_gives_the_same_gradient(dtype, inner):
-    """The densities a recomputed step writes are those the adjoint's own
-    density pass computes (same pulls, same summation order), so the cached
-    sweep reproduces the plain one bit for bit; a variant that writes no
-    densities falls back to the density pass."""
-    announce(f"density cache: {dtype}, inner {inner}")
+def test_moment_cache_gives_the_same_gradient(dtype, inner):
+    """The densities and momenta a recomputed step writes are those the
+    adjoint computes from its own pull (same pulls, same sums in the same
+    order), so the cached sweep reproduces the plain one bit for bit; a
+    variant that writes no moments falls back to the full path."""
+    announce(f"moment cache: {dtype}, inner {inner}")
     c = _tiny(0.1)
     c["params"] = dict(c["params"], dtype=dtype)
     nsteps, K, target = 40, 9, 115.0
     out = []
     for cache in (False, True):
         s = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
-                          inner=inner, density_cache=cache)
+                          inner=inner, moment_cache=cache)
         out.append((s.forward(), s.backward()))
     assert out[0] == out[1]
     reg = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
-                        inner=inner, density_cache=True)
+                        inner=inner, moment_cache=True)
     reg.lat.set_tile(scd.variant_index(64, 4, 0, 1), 4)
     ref = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target,
-                        inner=inner, density_cache=False)
+                        inner=inner, moment_cache=False)
     ref.lat.set_tile(scd.variant_index(64, 4, 0, 1), 4)
     assert (reg.forward(), reg.backward()) == (ref.forward(), ref.backward())
