@@ -141,30 +141,42 @@ struct CaGeom {
   }
 };
 
-// first crossing > 0 -> <= 0 of the column above k0, NaN if none
-__device__ double col_crossing(const CaGeom& g, const double* col, int k0) {
+// The column (ic, jc) and, per z-layer, its row y = jc and column x = ic:
+// everything the serial scans below read, staged in LDS so that each scan
+// step waits on LDS rather than on memory.
+struct LayerRC {
+  const double* row;  // phi(x, jc), x = 0 .. nx - 1
+  const double* col;  // phi(ic, y), y = 0 .. ny - 1
+  int jc;
+  __device__ double at(int x, int y) const { return y == jc ? row[x] : col[y]; }
+};
+
+// first crossing > 0 -> <= 0 of the column above k0 (colsolid: 1 at walls),
+// NaN if none
+__device__ double col_crossing(const CaGeom& g, const double* col, const double* colsolid,
+                               int k0) {
   for (int k = k0; k + 1 < g.nz; ++k) {
-    if (g.solid(g.c.ic, g.c.jc, k + 1)) break;
+    if (colsolid[k + 1] != 0.0) break;
     const double p0 = col[k], p1 = col[k + 1];
     if (p0 > 0.0 && p1 <= 0.0) return k + p0 / (p0 - p1);
   }
   return __builtin_nan("");
 }
 
-__device__ double layer_ray(const CaGeom& g, const double* layer, int sx, int sy, int* flags) {
+__device__ double layer_ray(const CaGeom& g, const LayerRC& layer, int sx, int sy, int* flags) {
   const int len = sx != 0 ? g.nx : g.ny;
   for (int m = 0; m < len / 2; ++m) {
     const int x0 = wrap_index(g.c.ic + m * sx, g.nx), y0 = wrap_index(g.c.jc + m * sy, g.ny);
     const int x1 = wrap_index(g.c.ic + (m + 1) * sx, g.nx);
     const int y1 = wrap_index(g.c.jc + (m + 1) * sy, g.ny);
-    const double p0 = layer[y0 * g.nx + x0], p1 = layer[y1 * g.nx + x1];
+    const double p0 = layer.at(x0, y0), p1 = layer.at(x1, y1);
     if (p0 > 0.0 && p1 <= 0.0) return m + p0 / (p0 - p1);
   }
   *flags |= 8;  // SCD_CA_RAY_LIMIT
   return (double)(len / 2);
 }
 
-__device__ double mean_ray(const CaGeom& g, const double* layer, int* flags) {
+__device__ double mean_ray(const CaGeom& g, const LayerRC& layer, int* flags) {
   return 0.25 * (layer_ray(g, layer, 1, 0, flags) + layer_ray(g, layer, -1, 0, flags) +
                  layer_ray(g, layer, 0, 1, flags) + layer_ray(g, layer, 0, -1, flags));
 }
@@ -194,8 +206,8 @@ enum {
 // indicator's transition band), so that A-rich regions of the layer that are
 // not this droplet (a wall film, a second droplet) are left out.  Infinite
 // (whole layer) when phi <= 0 on the column at the reference layer.
-__device__ double e2_window(const CaGeom& g, const double* ref) {
-  if (!(ref[g.c.jc * g.nx + g.c.ic] > 0.0)) return __builtin_inf();
+__device__ double e2_window(const CaGeom& g, const LayerRC& ref) {
+  if (!(ref.at(g.c.ic, g.c.jc) > 0.0)) return __builtin_inf();
   int f = 0;
   double r = layer_ray(g, ref, 1, 0, &f);
   r = fmax(r, layer_ray(g, ref, -1, 0, &f));
@@ -220,14 +232,34 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
                                                    const double* __restrict__ phi,
                                                    double* __restrict__ res) {
   __shared__ double sh[4 * 16];
+  extern __shared__ double stage[];  // ca_stage_bytes(nx, ny, nz)
   const CaGeom g{nx, ny, nz, links, c};
   const int A = nx * ny;
   const int kref = c.zs + c.off;
   const double* ref = phi;
   const double* low = phi + A;
-  const double* col = phi + 2 * A;
+  double* rowR = stage;
+  double* colR = rowR + nx;
+  double* rowL = colR + ny;
+  double* colL = rowL + nx;
+  double* col = colL + ny;
+  double* colsolid = col + nz;
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) {
+    rowR[t] = ref[c.jc * nx + t];
+    rowL[t] = low[c.jc * nx + t];
+  }
+  for (int t = threadIdx.x; t < ny; t += blockDim.x) {
+    colR[t] = ref[t * nx + c.ic];
+    colL[t] = low[t * nx + c.ic];
+  }
+  for (int t = threadIdx.x; t < nz; t += blockDim.x) {
+    col[t] = phi[2 * A + t];
+    colsolid[t] = g.solid(c.ic, c.jc, t) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const LayerRC refRC{rowR, colR, c.jc}, lowRC{rowL, colL, c.jc};
   // layer sums: sum chi inside the E2 window, centroid of phi > 0
-  const double rcut = e2_window(g, ref);
+  const double rcut = e2_window(g, refRC);
   double v[4] = {0, 0, 0, 0};
   for (int t = threadIdx.x; t < A; t += blockDim.x) {
     const int x = t % nx, y = t / nx;
@@ -254,13 +286,13 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
   } else {
     int flat = 0;
     if (col[kref] > 0.0) {
-      const double ztop = col_crossing(g, col, kref);
+      const double ztop = col_crossing(g, col, colsolid, kref);
       if (isnan(ztop)) {
         flags |= 16;
         out[R_TH1] = nan;
       } else {
         const double h = ztop - zw, H = ztop - kref;
-        const double aref = mean_ray(g, ref, &flags);
+        const double aref = mean_ray(g, refRC, &flags);
         double R, a;
         out[R_TH1] = cap_theta(aref * aref, H, h, &R, &a, &flat);
         if (flat) flags |= 2;
@@ -268,13 +300,13 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
       }
     } else {
       flags |= 1;  // SCD_CA_NO_REF
-      const double ztop = col_crossing(g, col, c.zs + 1);
+      const double ztop = col_crossing(g, col, colsolid, c.zs + 1);
       if (isnan(ztop)) {
         flags |= 16;
         out[R_TH1] = nan;
       } else {
         const double h = ztop - zw;
-        const double a = mean_ray(g, low, &flags);
+        const double a = mean_ray(g, lowRC, &flags);
         out[R_TH1] = 2.0 * atan2(h, a) * RAD2DEG;
         out[R_H1] = h; out[R_A1] = a; out[R_BH1] = ztop - kref; out[R_AREF1] = nan;
         out[R_R1] = (a * a + h * h) / (2.0 * h);
@@ -283,7 +315,7 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
     // E2
     if (isinf(rcut)) flags |= 128;  // SCD_CA_E2_WHOLE_LAYER
     auto chi = [&](int k) {
-      if (g.solid(c.ic, c.jc, k)) return 0.0;
+      if (colsolid[k] != 0.0) return 0.0;
       return smoothstep((col[k] + c.eps) / (2.0 * c.eps));
     };
     int kend = kref + 1;
@@ -332,8 +364,14 @@ hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* link
   else
     hipLaunchKernelGGL(k_ca_phi<float>, dim3(blocks), dim3(256), 0, s, (const float*)pop, links,
                        nx, ny, nz, cfg, phi_scratch);
-  hipLaunchKernelGGL(k_ca_finish, dim3(1), dim3(256), 0, s, links, nx, ny, nz, cfg, phi_scratch,
-                     result);
+  const size_t stage = (size_t)8 * (2 * (size_t)nx + 2 * (size_t)ny + 2 * (size_t)nz);
+  if (stage > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ca_finish,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ca_finish, dim3(1), dim3(256), stage, s, links, nx, ny, nz, cfg,
+                     phi_scratch, result);
   return hipGetLastError();
 }
 
