@@ -301,6 +301,60 @@ def sizes(dtype="f32", etas=(0.1, 0.2, 0.3, 0.35), boxes=((128, 40000), (256, 80
     return out
 
 
+def adjoint_cost(reps=20):
+    """Cost of the reverse step against the forward step, FP64 and FP32, on
+    the gradient box (64 x 64 x 48) and the throughput box (128 x 128 x 64):
+    reps plain adjoint steps (density pass, pulled populations), reps forward
+    steps, then a one-level checkpointed gradient over 2 * reps steps with
+    segments of reps steps, with and without the moment cache (the backward
+    sweeps give the same gradient bit for bit).  Times from HIP events on
+    the lattice's stream; run under rocprofv3 for per-kernel times."""
+    stream = torch.cuda.Stream()
+    out = []
+    for dt in ("f64", "f32"):
+        for name, c in (("64x64x48", W.config_gradient(dtype=dt)),
+                        ("128x128x64", W.config_throughput(delta=0.2, dtype=dt))):
+            L = B.Lattice(c["params"], c["solid"], adjoint=True, stream=stream)
+            L.init_equilibrium(c["rho_a"], c["rho_b"])
+            L.step(10)
+            st = L.get_state()
+            a = L.ca_seed(c["ca"], 1.0)
+            b = torch.empty_like(a)
+            L.adjoint_reset()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            # direct C calls (accumulating on the device, no synchronisation)
+            ps, pl = B._ptr(st), [B._ptr(a), B._ptr(b)]
+            torch.cuda.synchronize()
+            B.check(B.lib().scd_adjoint_step(L.h, ps, pl[0], pl[1], None))
+            e[0].record(stream)
+            for r in range(reps):
+                B.check(B.lib().scd_adjoint_step(L.h, ps, pl[r % 2], pl[1 - r % 2], None))
+            e[1].record(stream)
+            e[2].record(stream)
+            L.step(reps)
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            adj, fwd = e[0].elapsed_time(e[1]) / reps, e[2].elapsed_time(e[3]) / reps
+            del L, st, a, b
+            sweeps = {}
+            for cache in (False, True):
+                s = GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], 2 * reps, reps, c["ca"],
+                              120.0, stream=stream, moment_cache=cache)
+                s.forward()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = s.backward()
+                torch.cuda.synchronize()
+                sweeps[cache] = (time.perf_counter() - t0, g)
+                del s
+            torch.cuda.empty_cache()
+            out.append(emit({"exp": "adjoint_cost", "dtype": dt, "box": name, "forward_us": fwd * 1e3,
+                             "adjoint_us": adj * 1e3, "ratio": adj / fwd,
+                             "backward_sweep_s": sweeps[False][0], "backward_sweep_cached_s": sweeps[True][0],
+                             "same_gradient": sweeps[False][1] == sweeps[True][1]}))
+    return out
+
+
 def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000):
     """Droplet on a square array of posts (width 6, pitch 12, height 12) in
     a 384 x 384 x 192 box, wall asymmetry -0.3; then one adjoint pass over
@@ -343,7 +397,7 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "fit", "posts", "young", "sizes"])
+    ap.add_argument("what", choices=["sweep", "fit", "posts", "young", "sizes", "adjoint"])
     ap.add_argument("--box", type=int, default=None, help="sizes: run one box edge only")
     ap.add_argument("--dtype", default=None, help="f64 or f32 (posts default f32, others f64)")
     ap.add_argument("--steps", type=int, default=None)
@@ -364,6 +418,8 @@ def main():
         sizes(a.dtype or "f32", boxes=boxes)
     elif a.what == "young":
         young(a.dtype or "f64", a.steps or 20000)
+    elif a.what == "adjoint":
+        adjoint_cost()
     else:
         posts(a.steps or 100000, a.adjoint_steps, a.dtype or "f32")
 
