@@ -625,7 +625,7 @@ hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, c
 }
 
 // STREAM copy of n 8-byte words: the attainable HBM rate of a plain
-// read-once write-once sweep, against which the step's rate is judged.
+// read-once write-once sweep, the reference for the step's rate.
 __global__ __launch_bounds__(256) void k_stream_copy(const double* __restrict__ a,
                                                      double* __restrict__ b, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
