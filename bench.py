@@ -161,8 +161,8 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
     L = scd.Lattice(c["params"], c["solid"], adjoint=True, stream=stream)
     L.init_equilibrium(c["rho_a"], c["rho_b"])
     L.step(200)
-    st = L.get_state()
-    lam = L.ca_seed(c["ca"], 1.0)
+    st = L.get_state(blocked=True)
+    lam = L.ca_seed(c["ca"], 1.0, blocked=True)
     lam2 = torch.empty_like(lam)
     L.graph_capture(20)
     lib = scd.binding.lib()

@@ -21,13 +21,22 @@
  * Conventions
  *   - Node index i = (z * ny + y) * nx + x, x fastest; N = nx * ny * nz.
  *     All three axes are periodic; walls come only from the solid mask.
- *   - Population state ("pop"): structure of arrays, element
- *     pop[(a * 19 + k) * N + i] for species a in {0 = A, 1 = B} and
- *     velocity k in the order: rest; +x, -x, +y, -y, +z, -z;
+ *   - Populations C^a_k(x) for species a in {0 = A, 1 = B} and velocity k in
+ *     the order: rest; +x, -x, +y, -y, +z, -z;
  *     (+1,+1,0), (-1,-1,0), (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1),
  *     (+1,0,-1), (-1,0,+1), (0,+1,+1), (0,-1,-1), (0,+1,-1), (0,-1,+1).
  *     Element type double (SCD_F64) or float (SCD_F32).  The stored state is
  *     post-collision; entries at solid nodes are never read.
+ *   - "pop" layout (every population buffer the library reads or writes:
+ *     the state, checkpoints, the adjoint's lambda): blocked.  With
+ *     P = nx * ny, plane index c = y * nx + x, pb = ceil(P / 32) blocks per
+ *     plane and sp = 19 * 32 * pb * nz elements per species, element
+ *     (a, k, x, y, z) sits at
+ *         a * sp + ((z * pb + c / 32) * 19 + k) * 32 + c % 32.
+ *     A buffer holds 2 * sp elements (scd_sizes); the slots past P in the
+ *     last block of each plane are padding, never read.
+ *   - "plain" layout: structure of arrays, element (a * 19 + k) * N + i,
+ *     2 * 19 * N elements.  scd_pop_pack / scd_pop_unpack convert.
  *   - Density arrays are double, 2 * N elements, rho[a * N + i].
  *   - "d_" pointers are device pointers on the current HIP device; "h_"
  *     pointers are host pointers.  The caller allocates every device buffer
@@ -68,7 +77,8 @@ typedef int32_t scd_status;
 #define SCD_WITH_ADJOINT 1     /* scd_params.flags: reserve adjoint scratch */
 
 typedef struct {
-  int32_t nx, ny, nz;          /* each >= 1; 19 * N * sizeof(real) < 4 GiB */
+  int32_t nx, ny, nz;          /* each >= 1; sp * sizeof(real) < 4 GiB
+                                  (sp: elements per species, see above) */
   int32_t dtype;               /* SCD_F64 or SCD_F32 */
   int32_t psi;                 /* SCD_PSI_RHO or SCD_PSI_EXP */
   int32_t flags;               /* SCD_WITH_ADJOINT or 0 */
@@ -148,6 +158,14 @@ scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const dou
 /* Advance nsteps >= 0 time steps of Eq. (LBeqs) (asynchronous). */
 scd_status scd_step(scd_lattice* h, int64_t nsteps);
 int64_t scd_step_count(const scd_lattice* h);
+
+/* Plain <-> pop layout for a buffer of this handle's dims and dtype
+ * (device to device, on the handle's stream; no synchronisation).  d_plain
+ * holds 2 * 19 * N elements, d_blocked 2 * sp (padding slots of d_blocked
+ * are left untouched by pack).  The two buffers must not overlap and must be
+ * aligned to the element size; SCD_EINVAL otherwise. */
+scd_status scd_pop_pack(const scd_lattice* h, const void* d_plain, void* d_blocked);
+scd_status scd_pop_unpack(const scd_lattice* h, const void* d_blocked, void* d_plain);
 
 /* Copy the current state out / in (pop layout, device to device). */
 scd_status scd_get_state(scd_lattice* h, void* d_dst);

@@ -69,6 +69,8 @@ _PROTOS = {
     "scd_init_equilibrium": [_VP, _VP, _VP],
     "scd_step": [_VP, _I64],
     "scd_get_state": [_VP, _VP],
+    "scd_pop_pack": [_VP, _VP, _VP],
+    "scd_pop_unpack": [_VP, _VP, _VP],
     "scd_set_state": [_VP, _VP, _I64],
     "scd_fill_state": [_VP, _D],
     "scd_density": [_VP, _VP],
@@ -205,7 +207,9 @@ class Lattice:
         self.pop_bytes = pop_b.value
         self.dtype = _torch_dtype(self.sp)
         self.solid = torch.as_tensor(solid, dtype=torch.uint8).reshape(self.shape).to(self.device).contiguous()
-        self.pop = [torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        # population buffers in the library's blocked layout (flat)
+        self.pop_numel = self.pop_bytes // torch.empty((), dtype=self.dtype).element_size()
+        self.pop = [torch.empty(self.pop_numel, dtype=self.dtype, device=self.device) for _ in range(2)]
         self.work = _alloc_bytes(work_b.value, self.device)
         self.stream = stream
         h = ctypes.c_void_p()
@@ -255,16 +259,46 @@ class Lattice:
     def step_count(self):
         return lib().scd_step_count(self.h)
 
-    def get_state(self, out=None):
-        if out is None:
-            out = torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device)
+    # Population tensors: "plain" is (2, 19, nz, ny, nx), the order of the
+    # Python API; "blocked" is the library's flat layout (pop_numel
+    # elements), which the C calls read and write.  pack/unpack convert on
+    # the lattice's stream.
+    def empty_blocked(self):
+        return torch.empty(self.pop_numel, dtype=self.dtype, device=self.device)
+
+    def pack(self, plain, out=None):
+        plain = plain.to(device=self.device, dtype=self.dtype).contiguous()
+        if plain.numel() != 2 * 19 * self.N:
+            raise ValueError("plain population tensor must have 2 * 19 * N elements")
+        out = self.empty_blocked() if out is None else out
         self._after_torch()
-        check(lib().scd_get_state(self.h, _ptr(out)))
+        check(lib().scd_pop_pack(self.h, _ptr(plain), _ptr(out)))
         self._before_torch()
         return out
 
-    def set_state(self, src, step=0):
+    def unpack(self, blocked, out=None):
+        if blocked.numel() != self.pop_numel:
+            raise ValueError("blocked population tensor must have pop_numel elements")
+        if out is None:
+            out = torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device)
+        self._after_torch()
+        check(lib().scd_pop_unpack(self.h, _ptr(blocked), _ptr(out)))
+        self._before_torch()
+        return out
+
+    def get_state(self, out=None, blocked=False):
+        b = self.empty_blocked() if (out is None or not blocked) else out
+        self._after_torch()
+        check(lib().scd_get_state(self.h, _ptr(b)))
+        self._before_torch()
+        return b if blocked else self.unpack(b, out)
+
+    def set_state(self, src, step=0, blocked=False):
         src = src.to(device=self.device, dtype=self.dtype).contiguous()
+        if not blocked:
+            src = self.pack(src)
+        elif src.numel() != self.pop_numel:
+            raise ValueError("blocked population tensor must have pop_numel elements")
         self._after_torch()
         check(lib().scd_set_state(self.h, _ptr(src), int(step)))
         self._keep = (src,)
@@ -352,29 +386,30 @@ class Lattice:
         d["status"] = st
         return d
 
-    def ca_seed(self, cfg, dL_dtheta=1.0, out=None):
-        if out is None:
-            out = torch.empty((2, 19) + self.shape, dtype=self.dtype, device=self.device)
+    def ca_seed(self, cfg, dL_dtheta=1.0, out=None, blocked=False):
+        b = self.empty_blocked() if (out is None or not blocked) else out
         c = make_ca_cfg(cfg)
         self._after_torch()
-        check(lib().scd_ca_seed(self.h, ctypes.byref(c), float(dL_dtheta), _ptr(out)))
+        check(lib().scd_ca_seed(self.h, ctypes.byref(c), float(dL_dtheta), _ptr(b)))
         self._before_torch()
-        return out
+        return b if blocked else self.unpack(b, out)
 
-    def adjoint_step(self, state_t, lam_in, lam_out=None, accumulate=False):
+    def adjoint_step(self, state_t, lam_in, lam_out=None, accumulate=False, blocked=False):
         """One reverse step.  accumulate=True adds the parameter gradient to
-        the device accumulator (no synchronisation) and returns None for it."""
-        if lam_out is None:
-            lam_out = torch.empty_like(lam_in)
+        the device accumulator (no synchronisation) and returns None for it.
+        Population tensors are plain unless blocked=True."""
+        if blocked:
+            st, li = state_t, lam_in
+            lo = torch.empty_like(lam_in) if lam_out is None else lam_out
+        else:
+            st, li, lo = self.pack(state_t), self.pack(lam_in), self.empty_blocked()
         self._after_torch()
-        if accumulate:
-            check(lib().scd_adjoint_step(self.h, _ptr(state_t), _ptr(lam_in), _ptr(lam_out), None))
-            self._before_torch()
-            return lam_out, None
-        dp = (ctypes.c_double * 5)()
-        check(lib().scd_adjoint_step(self.h, _ptr(state_t), _ptr(lam_in), _ptr(lam_out), dp))
+        dp = None if accumulate else (ctypes.c_double * 5)()
+        check(lib().scd_adjoint_step(self.h, _ptr(st), _ptr(li), _ptr(lo), dp))
         self._before_torch()
-        return lam_out, list(dp)
+        if not blocked:
+            lo = self.unpack(lo, lam_out)
+        return lo, (None if accumulate else list(dp))
 
     def adjoint_reset(self):
         check(lib().scd_adjoint_reset(self.h))
@@ -516,6 +551,9 @@ class _View(Lattice):
         self.shape = (params["nz"], params["ny"], params["nx"])
         self.N = params["nx"] * params["ny"] * params["nz"]
         self.dtype = _torch_dtype(self.sp)
+        pop_b = ctypes.c_size_t()
+        check(lib().scd_sizes(ctypes.byref(self.sp), ctypes.byref(pop_b), None))
+        self.pop_numel = pop_b.value // torch.empty((), dtype=self.dtype).element_size()
 
     def close(self):
         self.h = None  # owned by the batch

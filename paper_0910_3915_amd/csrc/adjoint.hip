@@ -20,20 +20,21 @@
 
 namespace scd {
 
-// Streaming with bounce-back as in the forward step, addressed with 64-bit
-// element offsets from the state base.
+// Streaming with bounce-back as in the forward step, addressed with element
+// offsets from the state base.
 template <typename real>
-__device__ __forceinline__ void pull38_adj(const real* __restrict__ src, int N, int i,
+__device__ __forceinline__ void pull38_adj(const real* __restrict__ src, const PopGeo& g,
                                            const int (&xs)[3], const int (&ys)[3],
-                                           const int (&zs)[3], int nx, int ny, uint32_t lb,
+                                           const int (&zs)[3], int nx, uint32_t lb,
                                            real (&n)[38]) {
+  const uint32_t self = pop_slot(g, zs[1], ys[1] * nx + xs[1]);
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const int j = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const uint32_t j = pop_slot(g, zs[1 - CZ[k]], ys[1 - CY[k]] * nx + xs[1 - CX[k]]);
     const bool bb = (lb >> OPP[k]) & 1u;
-    const size_t off = bb ? (size_t)OPP[k] * N + i : (size_t)k * N + j;
+    const size_t off = bb ? self + (uint32_t)OPP[k] * PBLK : j + (uint32_t)k * PBLK;
     n[k] = src[off];
-    n[Q + k] = src[(size_t)Q * N + off];
+    n[Q + k] = src[(size_t)g.sp + off];
   }
 }
 
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
                                                    double* __restrict__ partials, int accumulate) {
   __shared__ double sh[5 * 16];
   const int N = nx * ny * nz;
+  const PopGeo pg = pop_geo(nx, ny, nz);
   const int stride = gridDim.x * blockDim.x;
   double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
   // The FP64 kernel holds one wave per SIMD, so nothing else hides its load
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       axis3(node % nx, nx, xs);
       axis3((node / nx) % ny, ny, ys);
       axis3(node / (nx * ny), nz, zs);
-      pull38_adj(C, N, node, xs, ys, zs, nx, ny, l, c);
+      pull38_adj(C, pg, xs, ys, zs, nx, l, c);
     }
   };
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
+    const uint32_t si = pop_slot(pg, zs[1], ys[1] * nx + xs[1]);
     real rho[2], j[2][3];
     if constexpr (CACHED) {
 #pragma unroll
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
         for (int d = 0; d < 3; ++d) j[a][d] = mom[(size_t)(2 + 3 * a + d) * N + i];
       }
     } else {
-      if (!PREFETCH) pull38_adj(C, N, i, xs, ys, zs, nx, ny, lb, n);
+      if (!PREFETCH) pull38_adj(C, pg, xs, ys, zs, nx, lb, n);
       moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
       moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
     }
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       const real uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        const real g = lam[(size_t)(a * Q + k) * N + i] * ph.inv_tau[a];
+        const real g = lam[a * (size_t)pg.sp + si + k * PBLK] * ph.inv_tau[a];
         const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
         const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
                        real(4.5) * s * s * s - real(4.5) * uu * s;
@@ -286,17 +289,19 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
                                                     const real* __restrict__ ef,
                                                     real* __restrict__ out) {
   const int N = nx * ny * nz;
+  const PopGeo pg = pop_geo(nx, ny, nz);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const uint32_t lb = links[i];
-    if (lb & SELF_SOLID) {
-#pragma unroll
-      for (int k = 0; k < 2 * Q; ++k) out[(size_t)k * N + i] = 0;
-      continue;
-    }
     int xs[3], ys[3], zs[3];
     axis3(i % nx, nx, xs);
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
+    const uint32_t si = pop_slot(pg, zs[1], ys[1] * nx + xs[1]);
+    if (lb & SELF_SOLID) {
+#pragma unroll
+      for (int k = 0; k < 2 * Q; ++k) out[(k / Q) * (size_t)pg.sp + si + (k % Q) * PBLK] = 0;
+      continue;
+    }
     real acc[2] = {0, 0};
     if constexpr (FUSED) stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
 #pragma unroll
@@ -310,15 +315,17 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
       real mu[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k)
-        mu[k] = D + Ex * CX[k] + Ey * CY[k] + Ez * CZ[k] + keep * lam[(size_t)(a * Q + k) * N + i];
+        mu[k] = D + Ex * CX[k] + Ey * CY[k] + Ez * CZ[k] +
+                keep * lam[a * (size_t)pg.sp + si + k * PBLK];
+      real* __restrict__ oa = out + a * (size_t)pg.sp;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (!((lb >> OPP[k]) & 1u)) {  // y - c_k is fluid: it pulled n_k(y)
-          const int x = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
-          out[(size_t)(a * Q + k) * N + x] = mu[k];
+          const uint32_t x = pop_slot(pg, zs[1 - CZ[k]], ys[1 - CY[k]] * nx + xs[1 - CX[k]]);
+          oa[x + k * PBLK] = mu[k];
         }
         if ((lb >> k) & 1u)  // y + c_k is a wall: n_{opp k}(y) came from C_k(y)
-          out[(size_t)(a * Q + k) * N + i] = mu[OPP[k]];
+          oa[si + k * PBLK] = mu[OPP[k]];
       }
     }
   }

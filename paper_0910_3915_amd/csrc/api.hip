@@ -45,6 +45,9 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t real_size(int dtype) { return dtype == SCD_F64 ? 8 : 4; }
 
+// Elements of one population buffer in the blocked layout (both species).
+size_t pop_elems(const scd_params* p) { return 2 * (size_t)pop_geo(p->nx, p->ny, p->nz).sp; }
+
 struct WorkLayout {
   size_t links, partials, result, phi, ca, planes, rho, adj_partials, adj_acc, adj_dparams, q, d, e,
       total;
@@ -83,9 +86,12 @@ scd_status validate(const scd_params* p) {
   if (N >= (double)(1 << 30)) return fail(SCD_EINVAL, "lattice too large (%.0f nodes)", N);
   if (p->nz >= 65536) return fail(SCD_EINVAL, "nz must be < 65536");
   if (p->dtype != SCD_F64 && p->dtype != SCD_F32) return fail(SCD_EINVAL, "bad dtype %d", p->dtype);
-  // 32-bit byte offsets within one species' 19 planes
-  if (19.0 * N * (p->dtype == SCD_F64 ? 8 : 4) >= 4294967296.0)
-    return fail(SCD_EUNSUPPORTED, "19 planes of %.0f nodes exceed 4 GiB per species", N);
+  // 32-bit byte offsets within one species (blocked layout: planes padded to
+  // whole 32-node blocks)
+  const double slots = 32.0 * std::ceil((double)p->nx * p->ny / 32.0) * p->nz;
+  if (19.0 * slots * (p->dtype == SCD_F64 ? 8 : 4) >= 4294967296.0)
+    return fail(SCD_EUNSUPPORTED, "19 velocities of %.0f node slots exceed 4 GiB per species",
+                slots);
   if (p->psi != SCD_PSI_RHO && p->psi != SCD_PSI_EXP) return fail(SCD_EINVAL, "bad psi %d", p->psi);
   for (int a = 0; a < 2; ++a) {
     if (!(p->tau[a] > 0.5) || !std::isfinite(p->tau[a]))
@@ -263,8 +269,7 @@ const char* scd_version(void) { return "scdrop 1.0 (gfx950)"; }
 scd_status scd_sizes(const scd_params* p, size_t* pop_bytes, size_t* work_bytes) {
   scd_status st = validate(p);
   if (st) return st;
-  const size_t N = (size_t)p->nx * p->ny * p->nz;
-  if (pop_bytes) *pop_bytes = 2 * Q * N * real_size(p->dtype);
+  if (pop_bytes) *pop_bytes = pop_elems(p) * real_size(p->dtype);
   if (work_bytes) *work_bytes = work_layout(p).total;
   return SCD_OK;
 }
@@ -337,8 +342,9 @@ scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const dou
   if (!h || !d_rho_a || !d_rho_b) return fail(SCD_EINVAL, "NULL argument");
   // the other buffer's wall-node entries are never written by a step: zero
   // it so that every state copy is fully defined
-  HIPCHK(launch_fill(h->p.dtype, h->pop[1 - h->cur], 2 * Q * h->N, 0.0, h->stream));
-  HIPCHK(launch_init(h->p.dtype, h->pop[h->cur], d_rho_a, d_rho_b, h->links(), (int)h->N, h->stream));
+  HIPCHK(launch_fill(h->p.dtype, h->pop[1 - h->cur], pop_elems(&h->p), 0.0, h->stream));
+  HIPCHK(launch_init(h->p.dtype, h->pop[h->cur], d_rho_a, d_rho_b, h->links(), h->p.nx, h->p.ny,
+                     h->p.nz, h->stream));
   h->step = 0;
   return SCD_OK;
 }
@@ -353,22 +359,43 @@ int64_t scd_step_count(const scd_lattice* h) { return h ? h->step : -1; }
 
 scd_status scd_get_state(scd_lattice* h, void* d_dst) {
   if (!h || !d_dst) return fail(SCD_EINVAL, "NULL argument");
-  HIPCHK(hipMemcpyAsync(d_dst, h->pop[h->cur], 2 * Q * h->N * real_size(h->p.dtype),
+  HIPCHK(hipMemcpyAsync(d_dst, h->pop[h->cur], pop_elems(&h->p) * real_size(h->p.dtype),
                         hipMemcpyDeviceToDevice, h->stream));
   return SCD_OK;
 }
 
 scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step) {
   if (!h || !d_src) return fail(SCD_EINVAL, "NULL argument");
-  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_src, 2 * Q * h->N * real_size(h->p.dtype),
+  HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_src, pop_elems(&h->p) * real_size(h->p.dtype),
                         hipMemcpyDeviceToDevice, h->stream));
   h->step = step;
   return SCD_OK;
 }
 
+// Repacking between the plain and the blocked population layouts.
+static scd_status pop_repack(const scd_lattice* h, const void* src, void* dst, bool to_blocked) {
+  if (!h || !src || !dst) return fail(SCD_EINVAL, "NULL argument");
+  const size_t rs = real_size(h->p.dtype);
+  const size_t plain = 2 * Q * h->N * rs, blocked = pop_elems(&h->p) * rs;
+  const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+  const size_t sn = to_blocked ? plain : blocked, dn = to_blocked ? blocked : plain;
+  if (s0 < d0 + dn && d0 < s0 + sn) return fail(SCD_EINVAL, "source and destination overlap");
+  if ((s0 | d0) % rs) return fail(SCD_EINVAL, "buffers must be aligned to the element size");
+  HIPCHK(launch_pop_repack(h->p.dtype, src, dst, h->p.nx, h->p.ny, h->p.nz, to_blocked, h->stream));
+  return SCD_OK;
+}
+
+scd_status scd_pop_pack(const scd_lattice* h, const void* d_plain, void* d_blocked) {
+  return pop_repack(h, d_plain, d_blocked, true);
+}
+
+scd_status scd_pop_unpack(const scd_lattice* h, const void* d_blocked, void* d_plain) {
+  return pop_repack(h, d_blocked, d_plain, false);
+}
+
 scd_status scd_fill_state(scd_lattice* h, double value) {
   if (!h) return fail(SCD_EINVAL, "NULL handle");
-  HIPCHK(launch_fill(h->p.dtype, h->pop[h->cur], 2 * Q * h->N, value, h->stream));
+  HIPCHK(launch_fill(h->p.dtype, h->pop[h->cur], pop_elems(&h->p), value, h->stream));
   return SCD_OK;
 }
 
@@ -460,13 +487,14 @@ double scd_huang_angle(const scd_params* p, double rho_in, double rho_out) {
 
 scd_status scd_density(scd_lattice* h, double* d_rho) {
   if (!h || !d_rho) return fail(SCD_EINVAL, "NULL argument");
-  HIPCHK(launch_density(h->p.dtype, h->pop[h->cur], h->links(), d_rho, (int)h->N, h->stream));
+  HIPCHK(launch_density(h->p.dtype, h->pop[h->cur], h->links(), d_rho, h->p.nx, h->p.ny, h->p.nz,
+                        h->stream));
   return SCD_OK;
 }
 
 scd_status scd_observables(scd_lattice* h, scd_obs* out) {
   if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
-  HIPCHK(launch_observables(h->p.dtype, h->pop[h->cur], h->links(), (int)h->N,
+  HIPCHK(launch_observables(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
                             h->wd(h->wl.partials), h->wd(h->wl.result), h->stream));
   double r[6];
   HIPCHK(hipMemcpyAsync(r, h->wd(h->wl.result), sizeof(r), hipMemcpyDeviceToHost, h->stream));
@@ -576,7 +604,7 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
     if (st) return st;
   }
   h->ckpt_base = h->step;
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   for (int64_t t = 0; t < nsteps; t += K) {
     HIPCHK(hipMemcpyAsync((char*)d_ckpt + (size_t)(t / K) * bytes, h->pop[h->cur], bytes,
                           hipMemcpyDeviceToDevice, h->stream));
@@ -606,7 +634,7 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // recomputed step reads, still takes the full path.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   const size_t mbytes = 8 * h->N * real_size(h->p.dtype);
   const bool cache = h->mom_cache && h->mom_cache_steps >= t1 - t0 - 1 &&
                      variant_writes_moments(h->variant);
@@ -639,7 +667,7 @@ scd_status scd_ckpt_moment_cache(scd_lattice* h, void* d_buf, int64_t nsteps) {
 // After a backward sweep the lattice holds the first checkpoint (step
 // ckpt_base), the start of the segment reversed last.
 static scd_status backward_finish(scd_lattice* h, const void* d_ckpt, double* h_grad) {
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_ckpt, bytes, hipMemcpyDeviceToDevice, h->stream));
   h->step = h->ckpt_base;
   return scd_adjoint_read(h, h_grad);
@@ -657,7 +685,7 @@ static scd_status backward_start(scd_lattice* h, int64_t nsteps, int64_t K, cons
   if (!d_ckpt || !d_lam) return fail(SCD_EINVAL, "NULL argument");
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   scd_ca ca;
   st = scd_contact_angle(h, cfg, &ca);
   if (st) return st;
@@ -676,7 +704,7 @@ scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const vo
   void* lam[2];
   scd_status st = backward_start(h, nsteps, K, d_ckpt, d_lam, cfg, target_deg, lam);
   if (st) return st;
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   int lc = 0;
   const int64_t nseg = (nsteps + K - 1) / K;
   for (int64_t s = nseg - 1; s >= 0; --s) {
@@ -695,7 +723,7 @@ scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_
   void* lam[2];
   scd_status st = backward_start(h, nsteps, K1, d_ckpt, d_lam, cfg, target_deg, lam);
   if (st) return st;
-  const size_t bytes = 2 * Q * h->N * real_size(h->p.dtype);
+  const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
   int lc = 0;
   const int64_t nseg = (nsteps + K1 - 1) / K1;
   for (int64_t s = nseg - 1; s >= 0; --s) {

@@ -25,6 +25,37 @@ constexpr double WEIGHT[Q] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 
 // c_k from x - c_k = x + c_{opp k}, so bit OPP[k] decides bounce-back.
 constexpr uint32_t SELF_SOLID = 1u;
 
+// Population buffers (the state C^a_k and the adjoint's lambda) are blocked.
+// Each species holds nz planes; a plane holds ceil(nx ny / 32) blocks of 32
+// consecutive plane indices c = y nx + x; a block stores its 19 velocities
+// one after another, 32 values each.  Element (a, k, z, c) sits at
+//   a sp + ((z pb + c / 32) 19 + k) 32 + c % 32.
+// One velocity of a 32-node row is one contiguous run and the 19 velocities
+// of the row share one block, so the pulls of a tile row stay within few
+// DRAM pages.  The slots of the last block of a plane past nx ny are padding,
+// never read.
+constexpr uint32_t PBLK = 32;
+struct PopGeo {
+  uint32_t pb;  // blocks per plane
+  uint32_t sp;  // elements per species: 19 * 32 * pb * nz
+};
+__host__ __device__ inline PopGeo pop_geo(int nx, int ny, int nz) {
+  PopGeo g;
+  g.pb = ((uint32_t)nx * (uint32_t)ny + PBLK - 1) / PBLK;
+  g.sp = (uint32_t)Q * PBLK * g.pb * (uint32_t)nz;
+  return g;
+}
+// Element offset, within one species, of velocity 0 of node (z, c); velocity
+// k adds k * PBLK.
+__host__ __device__ inline uint32_t pop_slot(const PopGeo& g, int z, int c) {
+  return ((uint32_t)z * g.pb + ((uint32_t)c >> 5)) * (Q * PBLK) + ((uint32_t)c & (PBLK - 1));
+}
+// The same for a node index i = z nx ny + c (P = nx ny).
+__host__ __device__ inline uint32_t pop_slot_i(const PopGeo& g, int i, int P) {
+  const int z = i / P;
+  return pop_slot(g, z, i - z * P);
+}
+
 // Physical parameters in the precision of the computation.
 template <typename real>
 struct Phys {
@@ -44,6 +75,7 @@ struct LatDev {
   const uint32_t* __restrict__ links;
   int nx, ny, nz;
   int N;                          // nx * ny * nz (< 2^31)
+  PopGeo geo;                     // layout of src and dst
   Phys<real> ph;
   // optional: the moments of the post-stream populations of src, as 8 fields
   // of N: rho^A, rho^B, j^A (x, y, z), j^B (x, y, z)
@@ -80,7 +112,7 @@ __device__ __forceinline__ int nbr_index(const int (&xs)[3], const int (&ys)[3],
 
 // Load of one value at a uniform base plus a 32-bit byte offset (lowers to
 // the scalar-base + 32-bit vector-offset form of the global load).  The host
-// guarantees 19 * N * sizeof(real) < 2^32, so offsets within one species fit.
+// guarantees sp * sizeof(real) < 2^32, so offsets within one species fit.
 template <typename real>
 __device__ __forceinline__ real ld_off(const char* __restrict__ base, uint32_t boff) {
   return *reinterpret_cast<const real*>(base + boff);
@@ -97,22 +129,23 @@ __device__ __forceinline__ void st_off_nt(char* __restrict__ base, uint32_t boff
 }
 
 // Streaming with mid-grid bounce-back (Sec. 2): the 38 post-stream
-// populations of fluid node i.  For each k the value comes from x - c_k, or
-// from the opposite population of x itself when x - c_k is a wall node.
+// populations of fluid node (xs[1], ys[1], zs[1]).  For each k the value
+// comes from x - c_k, or from the opposite population of x itself when
+// x - c_k is a wall node.
 template <typename real>
-__device__ __forceinline__ void pull38(const real* __restrict__ src, int N, int i,
+__device__ __forceinline__ void pull38(const real* __restrict__ src, const PopGeo& g,
                                        const int (&xs)[3], const int (&ys)[3], const int (&zs)[3],
-                                       int nx, int ny, uint32_t lb, real (&n)[38]) {
+                                       int nx, uint32_t lb, real (&n)[38]) {
   const char* __restrict__ pa = reinterpret_cast<const char*>(src);
-  const char* __restrict__ pb = reinterpret_cast<const char*>(src + (size_t)Q * N);
+  const char* __restrict__ pb = reinterpret_cast<const char*>(src + g.sp);
   constexpr uint32_t S = sizeof(real);
+  const uint32_t self = pop_slot(g, zs[1], ys[1] * nx + xs[1]);
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const int j = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const uint32_t j = pop_slot(g, zs[1 - CZ[k]], ys[1 - CY[k]] * nx + xs[1 - CX[k]]);
     const bool bb = (lb >> OPP[k]) & 1u;
-    // plane k at node j, or plane OPP[k] at node i
-    const uint32_t off = bb ? ((uint32_t)OPP[k] * (uint32_t)N + (uint32_t)i) * S
-                            : ((uint32_t)k * (uint32_t)N + (uint32_t)j) * S;
+    // velocity k at node x - c_k, or velocity OPP[k] at x
+    const uint32_t off = bb ? (self + (uint32_t)OPP[k] * PBLK) * S : (j + (uint32_t)k * PBLK) * S;
     n[k] = ld_off<real>(pa, off);
     n[Q + k] = ld_off<real>(pb, off);
   }
@@ -120,12 +153,12 @@ __device__ __forceinline__ void pull38(const real* __restrict__ src, int N, int 
 
 // Post-stream densities only (sums of the pulled populations).
 template <typename real>
-__device__ __forceinline__ void pull_density(const real* __restrict__ src, int N, int i,
+__device__ __forceinline__ void pull_density(const real* __restrict__ src, const PopGeo& g,
                                              const int (&xs)[3], const int (&ys)[3],
-                                             const int (&zs)[3], int nx, int ny, uint32_t lb,
+                                             const int (&zs)[3], int nx, uint32_t lb,
                                              real& ra, real& rb) {
   real n[38];
-  pull38(src, N, i, xs, ys, zs, nx, ny, lb, n);
+  pull38(src, g, xs, ys, zs, nx, lb, n);
   real a = 0, b = 0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {

@@ -32,9 +32,11 @@ inline Phys<real> phys_cast(const PhysD& d) {
 hipError_t launch_links(const uint8_t* solid, uint32_t* links, int nx, int ny, int nz,
                         hipStream_t s);
 hipError_t launch_init(int dtype, void* pop, const double* ra, const double* rb,
-                       const uint32_t* links, int N, hipStream_t s);
-hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int N,
-                          hipStream_t s);
+                       const uint32_t* links, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_pop_repack(int dtype, const void* src, void* dst, int nx, int ny, int nz,
+                             bool to_blocked, hipStream_t s);
+hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int nx,
+                          int ny, int nz, hipStream_t s);
 hipError_t launch_stream_density(int dtype, const void* pop, const uint32_t* links, void* rho,
                                  int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s);
@@ -60,8 +62,8 @@ constexpr int RED_BLOCKS = 512;   // blocks of the observable reductions
 constexpr int RED_STRIDE = 8;     // doubles per block partial
 // contact-angle result slots (doubles) in the work area
 constexpr int CA_SLOTS = 32;
-hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int N,
-                              double* partials, double* result, hipStream_t s);
+hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                              int nz, double* partials, double* result, hipStream_t s);
 struct CaDev {
   int ic, jc, zs, off;
   double eps;

@@ -45,15 +45,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 template <typename real>
 __global__ __launch_bounds__(256) void k_obs_partial(const real* __restrict__ pop,
                                                      const uint32_t* __restrict__ links, int N,
+                                                     int P, PopGeo g,
                                                      double* __restrict__ partials) {
   __shared__ double sh[6 * 16];
   double v[6] = {0, 0, 0, 0, 0, 0};  // mass A, mass B, Px, Py, Pz, non-finite count
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     if (links[i] & SELF_SOLID) continue;
+    const size_t si = pop_slot_i(g, i, P);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const double a = (double)pop[(size_t)k * N + i];
-      const double b = (double)pop[(size_t)(Q + k) * N + i];
+      const double a = (double)pop[si + k * PBLK];
+      const double b = (double)pop[g.sp + si + k * PBLK];
       if (!isfinite(a) || !isfinite(b)) v[5] += 1.0;
       v[0] += a;
       v[1] += b;
@@ -81,14 +83,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     for (int j = 0; j < nvals; ++j) result[j] = v[j];
 }
 
-hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int N,
-                              double* partials, double* result, hipStream_t s) {
+hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
+                              int nz, double* partials, double* result, hipStream_t s) {
+  const int N = nx * ny * nz, P = nx * ny;
+  const PopGeo g = pop_geo(nx, ny, nz);
   if (dtype == 0)
     hipLaunchKernelGGL(k_obs_partial<double>, dim3(RED_BLOCKS), dim3(256), 0, s,
-                       (const double*)pop, links, N, partials);
+                       (const double*)pop, links, N, P, g, partials);
   else
     hipLaunchKernelGGL(k_obs_partial<float>, dim3(RED_BLOCKS), dim3(256), 0, s,
-                       (const float*)pop, links, N, partials);
+                       (const float*)pop, links, N, P, g, partials);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, RED_BLOCKS, 6, result);
   return hipGetLastError();
 }
@@ -100,8 +104,9 @@ hipError_t launch_observables(int dtype, const void* pop, const uint32_t* links,
 template <typename real>
 __global__ void k_ca_phi(const real* __restrict__ pop, const uint32_t* __restrict__ links, int nx,
                          int ny, int nz, CaDev c, double* __restrict__ phi) {
-  const int A = nx * ny, N = A * nz;
+  const int A = nx * ny;
   const int total = 2 * A + nz;
+  const PopGeo g = pop_geo(nx, ny, nz);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
     int x, y, z;
     if (t < A) { x = t % nx; y = t / nx; z = c.zs + c.off; }
@@ -112,10 +117,11 @@ __global__ void k_ca_phi(const real* __restrict__ pop, const uint32_t* __restric
       const int i = (z * ny + y) * nx + x;
       if (!(links[i] & SELF_SOLID)) {
         double ra = 0, rb = 0;
+        const size_t si = pop_slot(g, z, y * nx + x);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          ra += (double)pop[(size_t)k * N + i];
-          rb += (double)pop[(size_t)(Q + k) * N + i];
+          ra += (double)pop[si + k * PBLK];
+          rb += (double)pop[g.sp + si + k * PBLK];
         }
         v = ra - rb;  // order parameter (Sec. 2)
       }
@@ -382,7 +388,8 @@ template <typename real>
 __global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, int nz, CaDev c,
                           const double* __restrict__ phi, const double* __restrict__ res,
                           double dL, real* __restrict__ lam) {
-  const int A = nx * ny, N = A * nz;
+  const int A = nx * ny;
+  const PopGeo pg = pop_geo(nx, ny, nz);
   const int kref = c.zs + c.off;
   const int kend = (int)res[R_KEND];
   const double dH = res[R_DTH_DH], dA = res[R_DTH_DA];
@@ -405,10 +412,11 @@ __global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, in
       gr = dH * dchi;
     }
     const real va = (real)(dL * gr), vb = (real)(-dL * gr);
+    const size_t si = pop_slot(pg, z, y * nx + x);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      lam[(size_t)k * N + i] = va;
-      lam[(size_t)(Q + k) * N + i] = vb;
+      lam[si + k * PBLK] = va;
+      lam[pg.sp + si + k * PBLK] = vb;
     }
   }
 }
@@ -416,8 +424,7 @@ __global__ void k_ca_seed(const uint32_t* __restrict__ links, int nx, int ny, in
 hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,
                           const double* phi_scratch, const double* result, double dL_dtheta,
                           void* lambda, hipStream_t s) {
-  const size_t N = (size_t)nx * ny * nz;
-  hipError_t e = launch_fill(dtype, lambda, 2 * Q * N, 0.0, s);
+  hipError_t e = launch_fill(dtype, lambda, 2 * (size_t)pop_geo(nx, ny, nz).sp, 0.0, s);
   if (e != hipSuccess) return e;
   const int total = nx * ny + nz;
   const int blocks = (total + 255) / 256;
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(256) void k_pressure(const real* __restrict__ pop,
       axis3((i / nx) % ny, ny, ys);
       axis3(i / (nx * ny), nz, zs);
       real n[38];
-      pull38(pop, N, i, xs, ys, zs, nx, ny, lb, n);
+      pull38(pop, pop_geo(nx, ny, nz), xs, ys, zs, nx, lb, n);
       double R = 0, j[3] = {0, 0, 0}, m[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -557,10 +564,12 @@ __global__ __launch_bounds__(256) void k_radial_split(const real* __restrict__ p
           v = pn - 0.5 * (p0 + p1 + p2 - pn);
         }
         double ra = 0, rb = 0;
+        const PopGeo g = pop_geo(nx, ny, nz);
+        const size_t si = pop_slot_i(g, i, nx * ny);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          ra += (double)pop[(size_t)k * N + i];
-          rb += (double)pop[(size_t)(Q + k) * N + i];
+          ra += (double)pop[si + k * PBLK];
+          rb += (double)pop[g.sp + si + k * PBLK];
         }
         ph = ra - rb;
       }
@@ -651,9 +660,11 @@ __global__ __launch_bounds__(256) void k_pull_copy(const real* __restrict__ src,
     axis3((i / nx) % ny, ny, ys);
     axis3(i / (nx * ny), nz, zs);
     real n[38];
-    pull38(src, N, i, xs, ys, zs, nx, ny, lb, n);
+    const PopGeo g = pop_geo(nx, ny, nz);
+    pull38(src, g, xs, ys, zs, nx, lb, n);
+    const size_t si = pop_slot(g, zs[1], ys[1] * nx + xs[1]);
 #pragma unroll
-    for (int k = 0; k < 38; ++k) dst[(size_t)k * N + i] = n[k];
+    for (int k = 0; k < 38; ++k) dst[(k / Q) * (size_t)g.sp + si + (k % Q) * PBLK] = n[k];
   }
 }
 

@@ -106,13 +106,13 @@ __device__ __forceinline__ void collide_node(const LatDev<real>& L, const real (
                   {upx + sB * fbx, upy + sB * fby, upz + sB * fbz}};
   const real rho[2] = {ra, rb};
   constexpr uint32_t S = sizeof(real);
-  const uint32_t N = (uint32_t)L.N;
+  const uint32_t si = pop_slot_i(L.geo, i, L.nx * L.ny);
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const real ux = u[a][0], uy = u[a][1], uz = u[a][2];
     const real uu = ux * ux + uy * uy + uz * uz;
     const real it = ph.inv_tau[a];
-    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * L.N);
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * L.geo.sp);
     real moving = 0;  // sum of the 18 moving equilibria
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
@@ -122,8 +122,8 @@ __device__ __forceinline__ void collide_node(const LatDev<real>& L, const real (
       equilibrium_pair(real(WEIGHT[k]) * rho[a], s, uu, fk, fo);
       moving += fk + fo;
       real nk = n[a * Q + k], no = n[a * Q + o];
-      st_off<real>(out, ((uint32_t)k * N + (uint32_t)i) * S, nk + (fk - nk) * it);
-      st_off<real>(out, ((uint32_t)o * N + (uint32_t)i) * S, no + (fo - no) * it);
+      st_off<real>(out, (si + (uint32_t)k * PBLK) * S, nk + (fk - nk) * it);
+      st_off<real>(out, (si + (uint32_t)o * PBLK) * S, no + (fo - no) * it);
     }
     // rest population: the equilibrium's zeroth moment is rho exactly, so
     // n^eq_0 = rho - sum of the moving ones (the same value as
@@ -131,7 +131,7 @@ __device__ __forceinline__ void collide_node(const LatDev<real>& L, const real (
     // floating point where the weights 1/3, 1/18, 1/36 are not)
     const real eq0 = rho[a] - moving;
     const real f0 = n[a * Q];
-    st_off<real>(out, (uint32_t)i * S, f0 + (eq0 - f0) * it);
+    st_off<real>(out, si * S, f0 + (eq0 - f0) * it);
   }
 }
 
@@ -152,7 +152,7 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   using T = Tile<TX, TY>;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
   int xs[3], ys[3];
@@ -207,16 +207,13 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
     E2<real>* slot = lds + (zr & 3) * T::P;
     real hm[T::HPT][38];
 #pragma unroll
-    for (int h = 0; h < T::HPT; ++h) {
-      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
-      if (!(lbh[h] & SELF_SOLID)) pull38(L.src, N, i, hx[h], hy[h], zs, nx, ny, lbh[h], hm[h]);
-    }
-    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
+    for (int h = 0; h < T::HPT; ++h)
+      if (!(lbh[h] & SELF_SOLID)) pull38(L.src, L.geo, hx[h], hy[h], zs, nx, lbh[h], hm[h]);
     solid_out = (lbi & SELF_SOLID) != 0;
     real m[38];
     if (!solid_out) {
-      if (keep) pull38(L.src, N, i, xs, ys, zs, nx, ny, lbi, nout);
-      else pull38(L.src, N, i, xs, ys, zs, nx, ny, lbi, m);
+      if (keep) pull38(L.src, L.geo, xs, ys, zs, nx, lbi, nout);
+      else pull38(L.src, L.geo, xs, ys, zs, nx, lbi, m);
     }
     uint32_t nli, nlh[T::HPT];
     load_links(zr + 1, nli, nlh);
@@ -285,7 +282,7 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
           force_sums<real, T::LX>(L.ph, lds + ((zc - 1) & 3) * T::P, lds + (zc & 3) * T::P,
                                   lds + ((zc + 1) & 3) * T::P, pos, S);
           phase_fence();
-          pull38(L.src, N, i, xs, ys, zs, nx, ny, lb, ncur);
+          pull38(L.src, L.geo, xs, ys, zs, nx, lb, ncur);
           collide_node<real>(L, ncur, S, i);
         }
       }
@@ -304,17 +301,17 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
 // species' force needs), so halo nodes need no exchange at all: a halo task
 // pulls one species' 19 populations of one node.
 template <typename real>
-__device__ __forceinline__ void pull19(const real* __restrict__ src, int N, int a, int i,
+__device__ __forceinline__ void pull19(const real* __restrict__ src, const PopGeo& g, int a,
                                        const int (&xs)[3], const int (&ys)[3], const int (&zs)[3],
-                                       int nx, int ny, uint32_t lb, real (&n)[19]) {
-  const char* __restrict__ base = reinterpret_cast<const char*>(src + (size_t)a * Q * N);
+                                       int nx, uint32_t lb, real (&n)[19]) {
+  const char* __restrict__ base = reinterpret_cast<const char*>(src + (size_t)a * g.sp);
   constexpr uint32_t S = sizeof(real);
+  const uint32_t self = pop_slot(g, zs[1], ys[1] * nx + xs[1]);
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const int j = nbr_index(xs, ys, zs, nx, ny, -CX[k], -CY[k], -CZ[k]);
+    const uint32_t j = pop_slot(g, zs[1 - CZ[k]], ys[1 - CY[k]] * nx + xs[1 - CX[k]]);
     const bool bb = (lb >> OPP[k]) & 1u;
-    const uint32_t off = bb ? ((uint32_t)OPP[k] * (uint32_t)N + (uint32_t)i) * S
-                            : ((uint32_t)k * (uint32_t)N + (uint32_t)j) * S;
+    const uint32_t off = bb ? (self + (uint32_t)OPP[k] * PBLK) * S : (j + (uint32_t)k * PBLK) * S;
     n[k] = ld_off<real>(base, off);
   }
 }
@@ -352,7 +349,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   const int a = lane >> 5;                          // species of this thread
   const int node = wave * 32 + (lane & 31);         // node of the tile
   const int tx = node % TX, ty = node / TX;
-  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
   int xs[3], ys[3];
@@ -417,24 +414,22 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
       if (!hval[h]) continue;
-      const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
       const bool wall = lbh[h] & SELF_SOLID;
       real r = 0;
       if (!wall) {
         real m[19];
-        pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lbh[h], m);
+        pull19(L.src, L.geo, hsp[h], hx[h], hy[h], zs, nx, lbh[h], m);
 #pragma unroll
         for (int k = 0; k < Q; ++k) r += m[k];
       }
       ring(zr, 1 - hsp[h])[hpos[h]] = e_from(L.ph, hsp[h], wall, r);
     }
     phase_fence();
-    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
     solid_out = (lbi & SELF_SOLID) != 0;
     real m[19];
     if (!solid_out) {
-      if (keep) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, nout);
-      else pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, m);
+      if (keep) pull19(L.src, L.geo, a, xs, ys, zs, nx, lbi, nout);
+      else pull19(L.src, L.geo, a, xs, ys, zs, nx, lbi, m);
     }
     load_links(zr + dir, lbi, lbh);
     real r = 0;
@@ -455,19 +450,17 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   auto plane_joint = [&](int zr, bool keep, real(&nout)[19], bool& solid_out) {
     int zs[3];
     axis3(wrap_index(zr, nz), nz, zs);
-    const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
     solid_out = (lbi & SELF_SOLID) != 0;
     real m[19];
     if (!solid_out) {
-      if (keep) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, nout);
-      else pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lbi, m);
+      if (keep) pull19(L.src, L.geo, a, xs, ys, zs, nx, lbi, nout);
+      else pull19(L.src, L.geo, a, xs, ys, zs, nx, lbi, m);
     }
     real hm[T::HPT][19];
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) {
-      const int ih = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
       if (!(lbh[h] & SELF_SOLID))
-        pull19(L.src, N, hsp[h], ih, hx[h], hy[h], zs, nx, ny, lbh[h], hm[h]);
+        pull19(L.src, L.geo, hsp[h], hx[h], hy[h], zs, nx, lbh[h], hm[h]);
     }
     uint32_t nli, nlh[T::HPT];
     load_links(zr + dir, nli, nlh);
@@ -548,8 +541,8 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
       const real uz = (jAz * itA + jBz * itB) * iR + sh * (-psi_a * sz);
       const real uu = ux * ux + uy * uy + uz * uz;
       const real it = ph.inv_tau[a];
-      const int i = (zc * ny + ys[1]) * nx + xs[1];
-      char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+      const uint32_t si = pop_slot(L.geo, zc, ys[1] * nx + xs[1]);
+      char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * L.geo.sp);
       constexpr uint32_t S = sizeof(real);
       real moving = 0;
 #pragma unroll
@@ -559,11 +552,11 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
         real fk, fo;
         equilibrium_pair(real(WEIGHT[k]) * rho, s, uu, fk, fo);
         moving += fk + fo;
-        store(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, ncur[k] + (fk - ncur[k]) * it);
-        store(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, ncur[o] + (fo - ncur[o]) * it);
+        store(out, (si + (uint32_t)k * PBLK) * S, ncur[k] + (fk - ncur[k]) * it);
+        store(out, (si + (uint32_t)o * PBLK) * S, ncur[o] + (fo - ncur[o]) * it);
       }
       const real eq0 = rho - moving;
-      store(out, (uint32_t)i * S, ncur[0] + (eq0 - ncur[0]) * it);
+      store(out, si * S, ncur[0] + (eq0 - ncur[0]) * it);
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) ncur[k] = nnext[k];
@@ -579,16 +572,16 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
 // (RS >= 2G + 2): an iteration writes the slots of its G new planes while
 // the previous iteration's collisions may still read the G + 2 before them.
 // Byte offsets of the nine columns (x + dx, y + dy) around a node within one
-// z plane, indexed [1 + dy][1 + dx]: with a plane's byte offset, every
-// neighbour of the node is one addition away.
+// z plane of one species, indexed [1 + dy][1 + dx]: with a plane's byte
+// offset, every neighbour of the node is one addition away.
 template <typename real>
-__device__ __forceinline__ void column_offsets(const int (&xs)[3], const int (&ys)[3], int nx,
-                                               uint32_t (&o)[3][3]) {
+__device__ __forceinline__ void column_offsets(const PopGeo& g, const int (&xs)[3],
+                                               const int (&ys)[3], int nx, uint32_t (&o)[3][3]) {
 #pragma unroll
   for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx)
-      o[dy][dx] = ((uint32_t)ys[dy] * (uint32_t)nx + (uint32_t)xs[dx]) * (uint32_t)sizeof(real);
+      o[dy][dx] = pop_slot(g, 0, ys[dy] * nx + xs[dx]) * (uint32_t)sizeof(real);
 }
 
 // The pull of pull19 from precomputed column offsets and the byte offsets
@@ -655,19 +648,19 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
     hpos[h] = (ly + 1) * T::LX + (lx + 1);
   }
 
-  // byte offsets: one species (NS), one z plane (PS), the columns around the
+  // byte offsets: one velocity (NS), one z plane (PS), the columns around the
   // thread's node and halo nodes; per-species bases of the source state
   constexpr uint32_t S = sizeof(real);
-  const uint32_t NS = (uint32_t)N * S, PS = (uint32_t)(nx * ny) * S;
+  const uint32_t NS = PBLK * S, PS = L.geo.pb * (Q * PBLK) * S;
   uint32_t col[3][3], hcol[T::HPT][3][3];
-  column_offsets<real>(xs, ys, nx, col);
-  const char* __restrict__ sbase = reinterpret_cast<const char*>(L.src + (size_t)a * Q * N);
+  column_offsets<real>(L.geo, xs, ys, nx, col);
+  const char* __restrict__ sbase = reinterpret_cast<const char*>(L.src + (size_t)a * L.geo.sp);
   const char* __restrict__ hbase[T::HPT];
   int hidx[T::HPT];
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
-    column_offsets<real>(hx[h], hy[h], nx, hcol[h]);
-    hbase[h] = reinterpret_cast<const char*>(L.src + (size_t)hsp[h] * Q * N);
+    column_offsets<real>(L.geo, hx[h], hy[h], nx, hcol[h]);
+    hbase[h] = reinterpret_cast<const char*>(L.src + (size_t)hsp[h] * L.geo.sp);
     hidx[h] = hy[h][1] * nx + hx[h][1];
   }
   const int cidx = ys[1] * nx + xs[1];
@@ -772,7 +765,7 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
     const real uu = ux * ux + uy * uy + uz * uz;
     const real it = ph.inv_tau[a];
     const uint32_t iS = (uint32_t)zc * PS + col[1][1];
-    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * L.geo.sp);
     real moving = 0;
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
@@ -862,7 +855,7 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
   const int a = lane >> 5;
   const int node = wave * 32 + (lane & 31);
   const int tx = node % TX, ty = node / TX;
-  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
   int xs[3], ys[3];
@@ -908,12 +901,12 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
       const int i = (zs[1] * ny + hy[h][1]) * nx + hx[h][1];
       const uint32_t lb = L.links[i];
       hw[h] = lb & SELF_SOLID;
-      if (!hw[h]) pull19(L.src, N, hsp[h], i, hx[h], hy[h], zs, nx, ny, lb, hm[h]);
+      if (!hw[h]) pull19(L.src, L.geo, hsp[h], hx[h], hy[h], zs, nx, lb, hm[h]);
     }
     const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
     const uint32_t lb = L.links[i];
     solid_out = (lb & SELF_SOLID) != 0;
-    if (!solid_out) pull19(L.src, N, a, i, xs, ys, zs, nx, ny, lb, nout);
+    if (!solid_out) pull19(L.src, L.geo, a, xs, ys, zs, nx, lb, nout);
   };
   // e values of plane zr from the loaded populations
   auto finish_plane = [&](int zr, const real(&nin)[19], bool solid_in) {
@@ -966,8 +959,8 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
     const real uz = (jAz * itA + jBz * itB) * iR + shf * (-psi_a * sz);
     const real uu = ux * ux + uy * uy + uz * uz;
     const real it = ph.inv_tau[a];
-    const int i = (zc * ny + ys[1]) * nx + xs[1];
-    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * Q * N);
+    const uint32_t si = pop_slot(L.geo, zc, ys[1] * nx + xs[1]);
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * L.geo.sp);
     constexpr uint32_t S = sizeof(real);
     real moving = 0;
 #pragma unroll
@@ -977,11 +970,11 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
       real fk, fo;
       equilibrium_pair(real(WEIGHT[k]) * rho, s, uu, fk, fo);
       moving += fk + fo;
-      st_off_nt<real>(out, ((uint32_t)k * (uint32_t)N + (uint32_t)i) * S, n[k] + (fk - n[k]) * it);
-      st_off_nt<real>(out, ((uint32_t)o * (uint32_t)N + (uint32_t)i) * S, n[o] + (fo - n[o]) * it);
+      st_off_nt<real>(out, (si + (uint32_t)k * PBLK) * S, n[k] + (fk - n[k]) * it);
+      st_off_nt<real>(out, (si + (uint32_t)o * PBLK) * S, n[o] + (fo - n[o]) * it);
     }
     const real eq0 = rho - moving;
-    st_off_nt<real>(out, (uint32_t)i * S, n[0] + (eq0 - n[0]) * it);
+    st_off_nt<real>(out, si * S, n[0] + (eq0 - n[0]) * it);
   };
 
   // prologue: planes za - 1 and za
@@ -1120,28 +1113,48 @@ __global__ void k_links(const uint8_t* __restrict__ solid, uint32_t* __restrict_
 // Sec. 2 initial state: fluid at rest, C_k = zeta_k rho.
 template <typename real>
 __global__ void k_init(real* __restrict__ pop, const double* __restrict__ ra,
-                       const double* __restrict__ rb, const uint32_t* __restrict__ links, int N) {
+                       const double* __restrict__ rb, const uint32_t* __restrict__ links, int N,
+                       int P, PopGeo g) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const bool solid = links[i] & SELF_SOLID;
+    const size_t si = pop_slot_i(g, i, P);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      pop[(size_t)k * N + i] = solid ? real(0) : real(WEIGHT[k] * ra[i]);
-      pop[(size_t)(Q + k) * N + i] = solid ? real(0) : real(WEIGHT[k] * rb[i]);
+      pop[si + k * PBLK] = solid ? real(0) : real(WEIGHT[k] * ra[i]);
+      pop[g.sp + si + k * PBLK] = solid ? real(0) : real(WEIGHT[k] * rb[i]);
     }
+  }
+}
+
+// Between the blocked population layout and the plain one, element
+// (a * 19 + k) * N + i.  Threads run over the plain index, node fastest, so
+// both sides are read and written in runs of 32 or more.  Padding slots of
+// the blocked buffer are left as they are.
+template <typename real, bool TO_BLOCKED>
+__global__ void k_pop_repack(const real* __restrict__ src, real* __restrict__ dst, int N, int P,
+                             PopGeo g) {
+  const size_t total = (size_t)2 * Q * N;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(e / N), i = (int)(e - (size_t)q * N);
+    const size_t b = (q / Q) * (size_t)g.sp + pop_slot_i(g, i, P) + (q % Q) * PBLK;
+    if (TO_BLOCKED) dst[b] = src[e];
+    else dst[e] = src[b];
   }
 }
 
 // rho^a = sum_k C_k^a of the stored state, FP64 output rho[a * N + i].
 template <typename real>
 __global__ void k_density(const real* __restrict__ pop, const uint32_t* __restrict__ links,
-                          double* __restrict__ rho, int N) {
+                          double* __restrict__ rho, int N, int P, PopGeo g) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     double ra = 0, rb = 0;
     if (!(links[i] & SELF_SOLID)) {
+      const size_t si = pop_slot_i(g, i, P);
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        ra += (double)pop[(size_t)k * N + i];
-        rb += (double)pop[(size_t)(Q + k) * N + i];
+        ra += (double)pop[si + k * PBLK];
+        rb += (double)pop[g.sp + si + k * PBLK];
       }
     }
     rho[i] = ra;
@@ -1162,7 +1175,7 @@ __global__ void k_stream_density(const real* __restrict__ pop, const uint32_t* _
       axis3(i % nx, nx, xs);
       axis3((i / nx) % ny, ny, ys);
       axis3(i / (nx * ny), nz, zs);
-      pull_density(pop, N, i, xs, ys, zs, nx, ny, lb, ra, rb);
+      pull_density(pop, pop_geo(nx, ny, nz), xs, ys, zs, nx, lb, ra, rb);
     }
     rho[i] = ra;
     rho[(size_t)N + i] = rb;
@@ -1191,24 +1204,51 @@ hipError_t launch_links(const uint8_t* solid, uint32_t* links, int nx, int ny, i
 }
 
 hipError_t launch_init(int dtype, void* pop, const double* ra, const double* rb,
-                       const uint32_t* links, int N, hipStream_t s) {
+                       const uint32_t* links, int nx, int ny, int nz, hipStream_t s) {
+  const int N = nx * ny * nz, P = nx * ny;
+  const PopGeo g = pop_geo(nx, ny, nz);
   if (dtype == 0)
     hipLaunchKernelGGL(k_init<double>, dim3(grid_for(N, 256)), dim3(256), 0, s, (double*)pop, ra,
-                       rb, links, N);
+                       rb, links, N, P, g);
   else
     hipLaunchKernelGGL(k_init<float>, dim3(grid_for(N, 256)), dim3(256), 0, s, (float*)pop, ra, rb,
-                       links, N);
+                       links, N, P, g);
   return hipGetLastError();
 }
 
-hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int N,
-                          hipStream_t s) {
+hipError_t launch_pop_repack(int dtype, const void* src, void* dst, int nx, int ny, int nz,
+                             bool to_blocked, hipStream_t s) {
+  const int N = nx * ny * nz, P = nx * ny;
+  const PopGeo g = pop_geo(nx, ny, nz);
+  const size_t total = (size_t)2 * Q * N;
+  const size_t gb = (total + 255) / 256;
+  const unsigned grid = (unsigned)(gb > 65536 ? 65536 : gb);
+#define SCD_REPACK(T)                                                                            \
+  if (to_blocked)                                                                                \
+    hipLaunchKernelGGL((k_pop_repack<T, true>), dim3(grid), dim3(256), 0, s, (const T*)src,       \
+                       (T*)dst, N, P, g);                                                        \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_pop_repack<T, false>), dim3(grid), dim3(256), 0, s, (const T*)src,      \
+                       (T*)dst, N, P, g);
+  if (dtype == 0) {
+    SCD_REPACK(double)
+  } else {
+    SCD_REPACK(float)
+  }
+#undef SCD_REPACK
+  return hipGetLastError();
+}
+
+hipError_t launch_density(int dtype, const void* pop, const uint32_t* links, double* rho, int nx,
+                          int ny, int nz, hipStream_t s) {
+  const int N = nx * ny * nz, P = nx * ny;
+  const PopGeo g = pop_geo(nx, ny, nz);
   if (dtype == 0)
     hipLaunchKernelGGL(k_density<double>, dim3(grid_for(N, 256)), dim3(256), 0, s,
-                       (const double*)pop, links, rho, N);
+                       (const double*)pop, links, rho, N, P, g);
   else
     hipLaunchKernelGGL(k_density<float>, dim3(grid_for(N, 256)), dim3(256), 0, s,
-                       (const float*)pop, links, rho, N);
+                       (const float*)pop, links, rho, N, P, g);
   return hipGetLastError();
 }
 
@@ -1288,11 +1328,11 @@ hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* li
                        hipStream_t s, void* mom_out) {
   if (dtype == 0) {
     LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
-                     phys_cast<double>(ph), (double*)mom_out};
+                     pop_geo(nx, ny, nz), phys_cast<double>(ph), (double*)mom_out};
     return launch_step_t(L, variant, zc, remap, s);
   }
   LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
-                  phys_cast<float>(ph), (float*)mom_out};
+                  pop_geo(nx, ny, nz), phys_cast<float>(ph), (float*)mom_out};
   return launch_step_t(L, variant, zc, remap, s);
 }
 
@@ -1332,11 +1372,11 @@ void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_
                  int ny, int nz, const PhysD& ph) {
   if (dtype == 0) {
     LatDev<double> L{(const double*)src, (double*)dst, links, nx, ny, nz, nx * ny * nz,
-                     phys_cast<double>(ph), nullptr};
+                     pop_geo(nx, ny, nz), phys_cast<double>(ph), nullptr};
     *(LatDev<double>*)out = L;
   } else {
     LatDev<float> L{(const float*)src, (float*)dst, links, nx, ny, nz, nx * ny * nz,
-                    phys_cast<float>(ph), nullptr};
+                    pop_geo(nx, ny, nz), phys_cast<float>(ph), nullptr};
     *(LatDev<float>*)out = L;
   }
 }

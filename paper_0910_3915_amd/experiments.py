@@ -317,8 +317,8 @@ def adjoint_cost(reps=20):
             L = B.Lattice(c["params"], c["solid"], adjoint=True, stream=stream)
             L.init_equilibrium(c["rho_a"], c["rho_b"])
             L.step(10)
-            st = L.get_state()
-            a = L.ca_seed(c["ca"], 1.0)
+            st = L.get_state(blocked=True)
+            a = L.ca_seed(c["ca"], 1.0, blocked=True)
             b = torch.empty_like(a)
             L.adjoint_reset()
             e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

@@ -40,7 +40,7 @@ class GradSetup:
         self.rho_a = None if rho_a is None else B._device_f64(rho_a, dev).reshape(-1)
         self.rho_b = None if rho_b is None else B._device_f64(rho_b, dev).reshape(-1)
         nseg = (self.nsteps + self.K - 1) // self.K
-        shape = (2, 19) + self.lat.shape
+        shape = (self.lat.pop_numel,)  # one population buffer (blocked layout)
         dt = self.lat.dtype
         self.ckpt = torch.empty((nseg,) + shape, dtype=dt, device=dev)
         if self.K2:

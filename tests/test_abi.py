@@ -50,6 +50,20 @@ def test_sizes_and_validation():
         assert scd.lib().scd_last_error()
 
 
+def test_pop_buffer_is_blocked_with_padded_planes():
+    """Population buffers hold 2 species x nz planes x ceil(nx ny / 32)
+    blocks x 19 velocities x 32 slots; the per-species 4 GiB bound of the
+    32-bit offsets counts the padded slots."""
+    for (nx, ny, nz) in ((20, 18, 14), (7, 5, 3), (33, 1, 2)):
+        st, pop, _ = _sizes(W.params(nx, ny, nz, 0.1))
+        assert st == 0
+        assert pop == 2 * 19 * 32 * ((nx * ny + 31) // 32) * nz * 8, (nx, ny, nz)
+    assert _sizes(W.params(256, 256, 256, 0.1))[0] == 0          # 2.55 GB per species
+    st, _, _ = _sizes(W.params(320, 320, 320, 0.1))
+    assert st == B.SCD_EUNSUPPORTED                              # 4.98 GB per species
+    assert _sizes(W.params(320, 320, 320, 0.1, dtype="f32"))[0] == 0
+
+
 def test_adjoint_flag_grows_work_area():
     p = W.params(16, 16, 12, 0.1)
     sp0, sp1 = B.make_params(p), B.make_params(p, adjoint=True)

@@ -1,0 +1,61 @@
+"""The blocked population layout: scd_pop_pack places element (a, k, x, y, z)
+where the header's formula says, scd_pop_unpack inverts it, and a state set
+in the plain order comes back unchanged."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_0910_3915_amd as scd
+from gpu_helpers import announce
+
+B = scd.binding
+pytestmark = pytest.mark.gpu
+
+
+def blocked_index(nx, ny, nz):
+    """Flat blocked offset of every plain element, shape (2, 19, nz, ny, nx),
+    from the formula a sp + ((z pb + c // 32) 19 + k) 32 + c % 32."""
+    pb = (nx * ny + 31) // 32
+    sp = 19 * 32 * pb * nz
+    a = np.arange(2).reshape(2, 1, 1, 1, 1)
+    k = np.arange(19).reshape(1, 19, 1, 1, 1)
+    z = np.arange(nz).reshape(1, 1, nz, 1, 1)
+    c = (np.arange(ny).reshape(ny, 1) * nx + np.arange(nx).reshape(1, nx)).reshape(1, 1, 1, ny, nx)
+    return a * sp + ((z * pb + c // 32) * 19 + k) * 32 + c % 32, 2 * sp
+
+
+@pytest.mark.parametrize("dims", [(20, 18, 14), (7, 5, 3), (64, 2, 5)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pack_follows_the_formula_and_unpack_inverts_it(dims, dtype):
+    import workloads as W
+    nx, ny, nz = dims
+    announce(f"pop pack/unpack: {dims} {dtype}")
+    L = scd.Lattice(W.params(nx, ny, nz, 0.1, dtype=dtype), np.zeros((nz, ny, nx), np.uint8))
+    idx, total = blocked_index(nx, ny, nz)
+    assert L.pop_numel == total
+    g = torch.Generator(device="cpu").manual_seed(nx * 1000 + ny * 10 + nz)
+    plain = torch.randn((2, 19, nz, ny, nx), generator=g, dtype=L.dtype)
+    blocked = L.pack(plain.cuda())
+    torch.cuda.synchronize()
+    got = blocked.cpu().numpy()
+    assert np.array_equal(got[idx.reshape(-1)], plain.numpy().reshape(-1))
+    back = L.unpack(blocked)
+    torch.cuda.synchronize()
+    assert torch.equal(back.cpu(), plain)
+    # set_state / get_state in the plain order round-trip exactly
+    L.set_state(plain.cuda(), 7)
+    assert torch.equal(L.get_state().cpu(), plain)
+    assert L.step_count == 7
+
+
+def test_pack_rejects_overlap():
+    import workloads as W
+    announce("pop pack: overlapping buffers")
+    L = scd.Lattice(W.params(8, 8, 4, 0.1), np.zeros((4, 8, 8), np.uint8))
+    buf = torch.zeros(2 * L.pop_numel, dtype=torch.float64, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    q = ctypes.c_void_p(buf.data_ptr() + 8 * 64)
+    assert B.lib().scd_pop_pack(L.h, p, q) == B.SCD_EINVAL
+    assert B.lib().scd_pop_unpack(L.h, p, None) == B.SCD_EINVAL

@@ -34,13 +34,14 @@ def test_pull_copy_is_the_streaming_step(dtype):
     L = scd.Lattice(c["params"], c["solid"])
     L.init_equilibrium(c["rho_a"], c["rho_b"])
     L.step(3)
-    before = L.get_state().clone()
+    before = L.get_state(blocked=True).clone()
     L.pull_copy()
     torch.cuda.synchronize()
-    assert torch.equal(L.get_state(), before)
+    assert torch.equal(L.get_state(blocked=True), before)
     other = L.pop[1] if torch.equal(L.pop[0], before) else L.pop[0]
     Lo = O.Lattice(W.params(20, 18, 14, 0.12), c["solid"])
-    want = O.to_gpu_layout(Lo.stream(O.from_gpu_layout(before.cpu().double().numpy())))
-    got = other.cpu().double().numpy()
+    plain = L.unpack(before)
+    want = O.to_gpu_layout(Lo.stream(O.from_gpu_layout(plain.cpu().double().numpy())))
+    got = L.unpack(other).cpu().double().numpy()
     fluid = c["solid"] == 0
     assert np.array_equal(got[:, :, fluid], want[:, :, fluid])
