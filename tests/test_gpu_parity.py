@@ -195,6 +195,26 @@ def test_full_size_one_step_fp64():
         assert abs(m1[a] - m0[a]) <= 1e-12 * m0[a]
 
 
+def test_largest_fp64_box_one_step():
+    """256^3 FP64 droplet, the largest cube the per-species 32-bit offsets
+    allow (2.55 GB per species in the blocked layout): one step from the
+    GPU's state after 20 steps must match the oracle's step from the same
+    state at every node."""
+    c = W.droplet_case(256, 256, 256, 70.0, 0.12, 0.2)
+    announce("parity: 256^3 FP64 droplet, state after 20 steps, one step vs oracle")
+    L = _run_gpu(c, 20)
+    s_t = gpu_state_as_oracle(L)
+    L.step(1)
+    got = gpu_state_as_oracle(L)
+    del L
+    Lo = O.Lattice(c["params"], c["solid"])
+    Lo.set_state(s_t)
+    del s_t
+    Lo.step(1)
+    d = np.max(np.abs(got - Lo.get_state()))
+    assert d <= 1e-14, d
+
+
 def test_full_size_one_step_fp32():
     c = W.config_throughput(delta=-0.2, dtype="f32")
     announce("parity: full size 128x128x64 FP32, one step vs oracle from the same state")
