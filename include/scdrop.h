@@ -281,9 +281,9 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
  * with two levels) and the step variant is a multi-plane march (6, 7 or 8),
  * each recomputed step also writes the densities and momenta of the
  * post-stream populations of the state it reads, and the adjoint of that
- * state uses them instead of running a density pass and pulling the
- * populations again.  These are the same sums in the same order, so the
- * gradient is the same bit for bit. */
+ * state uses them instead of pulling its populations to form them.  These
+ * are the same sums in the same order, so the gradient is the same bit for
+ * bit. */
 scd_status scd_ckpt_moment_cache(scd_lattice* h, void* d_buf, int64_t nsteps);
 scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t ckpt_every,
                              const void* d_ckpt, void* d_seg, void* d_lam,

@@ -55,12 +55,46 @@ __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
     }
 }
 
-// CACHED: rho and j come from mom (the moments a recomputed forward step
-// stored: rho^A, rho^B, j^A, j^B as 8 fields of N, the same sums as below)
-// and no population is pulled; rhof is then mom's first two fields.
-template <typename real, bool CACHED>
-__global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
-                                                   const real* __restrict__ mom,
+// Post-stream densities and momenta of the state a reverse step reads:
+// rho[a N + i] and jm[(3 a + d) N + i], zero at wall nodes.  These are the
+// sums of the pulled populations in the order of moments(), the same values
+// the forward step forms, so the reverse step built on them is exact.
+template <typename real>
+__global__ __launch_bounds__(256) void k_stream_moments(const real* __restrict__ C,
+                                                        const uint32_t* __restrict__ links,
+                                                        real* __restrict__ rho,
+                                                        real* __restrict__ jm, int nx, int ny,
+                                                        int nz) {
+  const int N = nx * ny * nz;
+  const PopGeo pg = pop_geo(nx, ny, nz);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const uint32_t lb = links[i];
+    real r[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (!(lb & SELF_SOLID)) {
+      int xs[3], ys[3], zs[3];
+      axis3(i % nx, nx, xs);
+      axis3((i / nx) % ny, ny, ys);
+      axis3(i / (nx * ny), nz, zs);
+      real n[38];
+      pull38_adj(C, pg, xs, ys, zs, nx, lb, n);
+      moments(&n[0], r[0], j[0][0], j[0][1], j[0][2]);
+      moments(&n[Q], r[1], j[1][0], j[1][1], j[1][2]);
+    }
+    rho[i] = r[0];
+    rho[(size_t)N + i] = r[1];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) jm[(size_t)(3 * a + d) * N + i] = j[a][d];
+  }
+}
+
+// Local part of the reverse step at every node.  rho comes from rhof and j
+// from jm (3 fields per species), both filled beforehand: by
+// k_stream_moments, or by a recomputed forward step of a checkpointed sweep
+// (its 8 stored fields: rho^A, rho^B, j^A, j^B); no population is pulled.
+template <typename real>
+__global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
                                                    const real* __restrict__ lam,
                                                    const uint32_t* __restrict__ links,
                                                    const real* __restrict__ rhof, int nx, int ny,
@@ -72,31 +106,9 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
   const PopGeo pg = pop_geo(nx, ny, nz);
   const int stride = gridDim.x * blockDim.x;
   double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
-  // The FP64 kernel holds one wave per SIMD, so nothing else hides its load
-  // latency: the next node's populations are requested once this node's
-  // neighbour densities are in, and arrive while its lambda' is read and
-  // its collision transposed.
-  constexpr bool PREFETCH = sizeof(real) == 8 && !CACHED;
-  auto fetch = [&](int node, uint32_t& l, real(&c)[38]) {
-    l = links[node];
-    if (!(l & SELF_SOLID)) {
-      int xs[3], ys[3], zs[3];
-      axis3(node % nx, nx, xs);
-      axis3((node / nx) % ny, ny, ys);
-      axis3(node / (nx * ny), nz, zs);
-      pull38_adj(C, pg, xs, ys, zs, nx, l, c);
-    }
-  };
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  real n[38];
-  uint32_t lnext = SELF_SOLID;
-  if (PREFETCH && i < N) fetch(i, lnext, n);
-  for (; i < N; i += stride) {
-    uint32_t lb;
-    if (PREFETCH) lb = lnext;
-    else lb = links[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const uint32_t lb = links[i];
     if (lb & SELF_SOLID) {
-      if (PREFETCH && i + stride < N) fetch(i + stride, lnext, n);
       for (int c = 0; c < 6; ++c) { qf[(size_t)c * N + i] = 0; ef[(size_t)c * N + i] = 0; }
       df[i] = 0;
       df[(size_t)N + i] = 0;
@@ -108,17 +120,11 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
     axis3(i / (nx * ny), nz, zs);
     const uint32_t si = pop_slot(pg, zs[1], ys[1] * nx + xs[1]);
     real rho[2], j[2][3];
-    if constexpr (CACHED) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        rho[a] = mom[(size_t)a * N + i];
+    for (int a = 0; a < 2; ++a) {
+      rho[a] = rhof[(size_t)a * N + i];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) j[a][d] = mom[(size_t)(2 + 3 * a + d) * N + i];
-      }
-    } else {
-      if (!PREFETCH) pull38_adj(C, pg, xs, ys, zs, nx, lb, n);
-      moments(&n[0], rho[0], j[0][0], j[0][1], j[0][2]);
-      moments(&n[Q], rho[1], j[1][0], j[1][1], j[1][2]);
+      for (int d = 0; d < 3; ++d) j[a][d] = jm[(size_t)(3 * a + d) * N + i];
     }
     real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
     // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k;
@@ -145,7 +151,6 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ C,
       pnb[k][0] = pA;
       pnb[k][1] = pB;
     }
-    if (PREFETCH && i + stride < N) fetch(i + stride, lnext, n);
     real F[2][3];
     for (int a = 0; a < 2; ++a)
       for (int d = 0; d < 3; ++d) F[a][d] = -psi[a] * S[a][d];
@@ -339,22 +344,22 @@ static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : ADJ_
 template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                             const uint32_t* links, int nx, int ny, int nz, const PhysD& phd,
-                            real* rhof, const real* mom, real* qf, real* df, real* ef,
+                            real* rhof, real* jf, const real* mom, real* qf, real* df, real* ef,
                             double* partials, int accumulate, hipStream_t s) {
   const Phys<real> ph = phys_cast<real>(phd);
   const size_t N = (size_t)nx * ny * nz;
+  const real* jm = jf;
   if (mom) {
-    rhof = const_cast<real*>(mom);  // its density fields, read only below
-    hipLaunchKernelGGL((k_adj_local<real, true>), dim3(adj_local_grid(sizeof(real))),
-                       dim3(256), 0, s, C, mom, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef,
-                       partials, accumulate);
+    // moments stored by the recomputed forward step: densities, then momenta
+    rhof = const_cast<real*>(mom);  // read only below
+    jm = mom + 2 * N;
   } else {
-    hipError_t e = launch_stream_density(sizeof(real) == 8 ? 0 : 1, C, links, rhof, nx, ny, nz, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adj_local<real, false>), dim3(adj_local_grid(sizeof(real))),
-                       dim3(256), 0, s, C, mom, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef,
-                       partials, accumulate);
+    const size_t g = (N + 255) / 256;
+    hipLaunchKernelGGL(k_stream_moments<real>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256),
+                       0, s, C, links, rhof, jf, nx, ny, nz);
   }
+  hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, jm,
+                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   // FP64 adds the transposed stencil inside the push pass (one fewer sweep
   // of D); in FP32 the gathers slow that pass more than the sweep costs
@@ -372,8 +377,8 @@ __global__ void k_sum5(const double* __restrict__ partials, int nblocks, double*
 
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
-                          void* rho_field, const void* mom_cached, void* q_field, void* d_field,
-                          void* e_field, double* partials, double* dparams_dev,
+                          void* rho_field, void* j_field, const void* mom_cached, void* q_field,
+                          void* d_field, void* e_field, double* partials, double* dparams_dev,
                           double* acc_partials, hipStream_t s) {
   // with acc_partials the block partials accumulate over steps and are summed
   // only when read (launch_adjoint_sum); otherwise this step's sum goes to
@@ -383,12 +388,12 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
   hipError_t e;
   if (dtype == 0)
     e = adjoint_t<double>((const double*)state_t, (const double*)lam_in, (double*)lam_out, links,
-                          nx, ny, nz, ph, (double*)rho_field, (const double*)mom_cached,
-                          (double*)q_field, (double*)d_field, (double*)e_field, part, accumulate,
-                          s);
+                          nx, ny, nz, ph, (double*)rho_field, (double*)j_field,
+                          (const double*)mom_cached, (double*)q_field, (double*)d_field,
+                          (double*)e_field, part, accumulate, s);
   else
     e = adjoint_t<float>((const float*)state_t, (const float*)lam_in, (float*)lam_out, links, nx,
-                         ny, nz, ph, (float*)rho_field, (const float*)mom_cached,
+                         ny, nz, ph, (float*)rho_field, (float*)j_field, (const float*)mom_cached,
                          (float*)q_field, (float*)d_field, (float*)e_field, part, accumulate, s);
   if (e != hipSuccess) return e;
   if (accumulate) return hipSuccess;

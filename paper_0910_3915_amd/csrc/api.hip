@@ -50,7 +50,7 @@ size_t pop_elems(const scd_params* p) { return 2 * (size_t)pop_geo(p->nx, p->ny,
 
 struct WorkLayout {
   size_t links, partials, result, phi, ca, planes, rho, adj_partials, adj_acc, adj_dparams, q, d, e,
-      total;
+      jm, total;
 };
 
 WorkLayout work_layout(const scd_params* p) {
@@ -73,6 +73,7 @@ WorkLayout work_layout(const scd_params* p) {
     w.q = take(6 * N * rs);
     w.d = take(2 * N * rs);
     w.e = take(6 * N * rs);
+    w.jm = take(6 * N * rs);  // post-stream momenta of the state a plain reverse step reads
   }
   w.total = off;
   return w;
@@ -545,7 +546,7 @@ static scd_status adjoint_enqueue(scd_lattice* h, const void* state_t, const voi
                                   void* lam_out, bool accumulate,
                                   const void* mom_cached = nullptr) {
   HIPCHK(launch_adjoint(h->p.dtype, state_t, lam_in, lam_out, h->links(), h->p.nx, h->p.ny,
-                        h->p.nz, h->ph, h->wv(h->wl.rho), mom_cached, h->wv(h->wl.q),
+                        h->p.nz, h->ph, h->wv(h->wl.rho), h->wv(h->wl.jm), mom_cached, h->wv(h->wl.q),
                         h->wv(h->wl.d), h->wv(h->wl.e), h->wd(h->wl.adj_partials),
                         h->wd(h->wl.adj_dparams),
                         accumulate ? h->wd(h->wl.adj_acc) : nullptr, h->stream));
@@ -629,9 +630,9 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // With a moment cache of at least t1 - t0 - 1 steps (and a step variant
 // that writes moments), each recomputed step also stores the densities and
 // momenta of the post-stream populations of the state it reads, and the
-// adjoint of that state reads them instead of running a density pass and
-// pulling the populations again; the last state of the segment, which no
-// recomputed step reads, still takes the full path.
+// adjoint of that state reads them instead of pulling its populations to
+// form them; for the last state of the segment, which no recomputed step
+// reads, the adjoint forms them itself.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
   const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);

@@ -96,8 +96,8 @@ constexpr int ADJ_BLOCKS = 2048;
 // caller) and launch_adjoint_sum reduces them when they are read.
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
-                          void* rho_field, const void* mom_cached, void* q_field, void* d_field,
-                          void* e_field, double* partials, double* dparams_dev,
+                          void* rho_field, void* j_field, const void* mom_cached, void* q_field,
+                          void* d_field, void* e_field, double* partials, double* dparams_dev,
                           double* acc_partials, hipStream_t s);
 hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s);
 hipError_t launch_zero(double* p, int n, hipStream_t s);

@@ -304,7 +304,7 @@ def sizes(dtype="f32", etas=(0.1, 0.2, 0.3, 0.35), boxes=((128, 40000), (256, 80
 def adjoint_cost(reps=20):
     """Cost of the reverse step against the forward step, FP64 and FP32, on
     the gradient box (64 x 64 x 48) and the throughput box (128 x 128 x 64):
-    reps plain adjoint steps (density pass, pulled populations), reps forward
+    reps plain adjoint steps (moments pass included), reps forward
     steps, then a one-level checkpointed gradient over 2 * reps steps with
     segments of reps steps, with and without the moment cache (the backward
     sweeps give the same gradient bit for bit).  Times from HIP events on

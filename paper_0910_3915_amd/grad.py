@@ -23,8 +23,8 @@ class GradSetup:
     forward pass from the lattice's current state instead of re-initialising.
     moment_cache keeps the densities and momenta of the post-stream
     populations of each recomputed segment (8 x N reals per step of a
-    segment), which spares the adjoint its density pass and its pull of the
-    populations; the gradient is the same bit for bit.
+    segment), which spares the adjoint its own pass over the populations to
+    form them; the gradient is the same bit for bit.
     """
 
     def __init__(self, params, solid, rho_a, rho_b, nsteps, ckpt_every, ca_cfg, target_deg,
