@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "D3Q19 2-comp MLUPS & % HBM roofline; adjoint/forward cost; FP32 vs FP64 dtheta"
-COUNTERS = os.path.join(ROOT, "profiles", "step_fused_128x128x64_f64_counters.json")
+COUNTERS = {dt: os.path.join(ROOT, "profiles", "step_fused_128x128x64_%s_counters.json" % dt)
+            for dt in ("f64", "f32")}
 KERNEL_SOURCES = ["paper_0910_3915_amd/csrc/step.hip", "paper_0910_3915_amd/csrc/common.hpp"]
 
 
@@ -111,12 +112,13 @@ def roofline(res, bytes_per_node, traffic):
                             "step_frac": round(achieved / layout, 4)}}
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    if not os.path.exists(COUNTERS):
+def measured_traffic(dtype):
+    """HBM bytes per launch of the step in this dtype from the committed
+    rocprofv3 counter summary, or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    if not os.path.exists(COUNTERS[dtype]):
         return None
-    d = json.load(open(COUNTERS))
+    d = json.load(open(COUNTERS[dtype]))
     if d.get("kernel_sha") != kernel_sha():
         return None
     return d.get("traffic_bytes_per_launch")
@@ -338,7 +340,12 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time every compiled variant first instead of the library defaults")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--dtype", choices=("f64", "f32"), default="f64",
+                    help="precision of the main workload; f32 times the FP32 relaxation run "
+                         "alone (no extras, no CPU baseline)")
     args = ap.parse_args()
+    if args.dtype == "f32":
+        args.no_extras = args.no_cpu = True
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(one process drives one GPU)", file=sys.stderr)
@@ -361,25 +368,28 @@ def main():
         tile32, ms32 = autotuned_tile(scd, W, "f32", stream)
         log(f"autotune: f64 {tile64} {ms64:.4f} ms/step, f32 {tile32} {ms32:.4f} ms/step")
 
-    log("timing FP64 relaxation run")
-    r64 = timed_relaxation(scd, W, torch, "f64", args.steps, args.warmup, args.obs_every, tile64, stream)
+    dt = args.dtype
+    log("timing %s relaxation run" % dt.upper())
+    r64 = timed_relaxation(scd, W, torch, dt, args.steps, args.warmup, args.obs_every,
+                           tile64 if dt == "f64" else tile32, stream)
     log(json.dumps(r64))
     result = {
         "metric": METRIC, "value": round(r64["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": r64["steps"], "warmup": args.warmup, "ms_per_step": round(r64["ms_per_step"], 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic (seeded droplet, no dataset)",
         "config": {"workload": "single droplet 128x128x64, cap r=24, g_ab=g_wall=0.12, tau=1, "
-                               "rho_wall=(0.6,0.4), FP64, observables every %d steps" % args.obs_every,
+                               "rho_wall=(0.6,0.4), %s, observables every %d steps"
+                               % (dt.upper(), args.obs_every),
                    "fluid_nodes": r64["fluid_nodes"], "tile": r64["tile"], "parallelism": "single GPU"},
-        "roofline": roofline(r64, 608, measured_traffic()),
+        "roofline": roofline(r64, 608 if dt == "f64" else 304, measured_traffic(dt)),
     }
     if not args.no_extras:
         log("timing FP32 relaxation run")
         r32 = timed_relaxation(scd, W, torch, "f32", args.steps, args.warmup, args.obs_every, tile32, stream)
         result["fp32"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
                           "ms_per_step": round(r32["ms_per_step"], 5), "tile": r32["tile"],
-                          "roofline": roofline(r32, 304, None)}
+                          "roofline": roofline(r32, 304, measured_traffic("f32"))}
         log("FP32 vs FP64 after %d steps" % args.theta_steps)
         result["fp32_vs_fp64"] = fp32_vs_fp64(scd, W, torch, args.theta_steps, tile64, tile32, stream)
         log("adjoint / forward cost")
