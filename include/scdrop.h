@@ -210,6 +210,16 @@ scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
 scd_status scd_radial_tension(scd_lattice* h, double* d_P, const double* h_center, double rmax,
                               int32_t nbins, double* h_profile, double* h_phi_profile,
                               double* h_Rs, double* h_gamma);
+/* The same with the minimum image taken only along the axes whose bit is set
+ * in periodic (bit 0 x, bit 1 y, bit 2 z); along the others d is the plain
+ * difference x - c.  scd_radial_tension is periodic = 7.  Use it for a
+ * droplet between walls (a sessile droplet: periodic = 3), whose shells
+ * must not wrap across the walls to the far side of the box.  periodic
+ * outside [0, 7]: SCD_EINVAL. */
+scd_status scd_radial_tension_axes(scd_lattice* h, double* d_P, const double* h_center,
+                                   int32_t periodic, double rmax, int32_t nbins,
+                                   double* h_profile, double* h_phi_profile, double* h_Rs,
+                                   double* h_gamma);
 
 /* Young's equation (Sec. 1, Eq. young) with the droplet species as the
  * liquid: theta = acos((gamma_SG - gamma_SL) / gamma_LG) in degrees, with

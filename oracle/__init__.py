@@ -95,6 +95,9 @@ def lib():
         L.ora_pressure_tensor.argtypes = [vp, dp]
         L.ora_radial_tension.restype = ctypes.c_double
         L.ora_radial_tension.argtypes = [vp, dp, ctypes.c_double, ctypes.c_int32, dp, dp, dp]
+        L.ora_radial_tension_axes.restype = ctypes.c_double
+        L.ora_radial_tension_axes.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                              dp, dp, dp]
         L.ora_young_angle.restype = ctypes.c_double
         L.ora_young_angle.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.ora_huang_angle.restype = ctypes.c_double
@@ -238,13 +241,16 @@ class Lattice:
         g = lib().ora_surface_tension_z(self._h, _dp(prof))
         return g, prof
 
-    def radial_tension(self, center, rmax, nbins):
-        """(gamma, R_s, profile of P_N - P_T, profile of phi) about center."""
+    def radial_tension(self, center, rmax, nbins, periodic=(True, True, True)):
+        """(gamma, R_s, profile of P_N - P_T, profile of phi) about center;
+        periodic: per axis, whether distances take the minimum image."""
         c = np.ascontiguousarray(center, np.float64)
         prof = np.zeros(nbins)
         pphi = np.zeros(nbins)
         rs = np.zeros(1)
-        g = lib().ora_radial_tension(self._h, _dp(c), float(rmax), int(nbins), _dp(prof), _dp(pphi), _dp(rs))
+        mask = sum(1 << a for a in range(3) if periodic[a])
+        g = lib().ora_radial_tension_axes(self._h, _dp(c), mask, float(rmax), int(nbins), _dp(prof),
+                                          _dp(pphi), _dp(rs))
         return g, rs[0], prof, pphi
 
     def contact_angle(self, cfg):

@@ -861,6 +861,15 @@ static double min_image(double d, int n) {
 
 double ora_radial_tension(ora_lattice* L, const double* center, double rmax, int nbins,
                           double* profile, double* phi_profile, double* Rs) {
+  return ora_radial_tension_axes(L, center, 7, rmax, nbins, profile, phi_profile, Rs);
+}
+
+/* The same with the minimum image only along the axes whose bit is set in
+ * periodic (bit 0 x, bit 1 y, bit 2 z).  A droplet in the droplet system of
+ * Sec. 4.1 rests on a wall: along the wall normal the box is bounded, and
+ * the distance from the droplet's centre is the plain difference.          */
+double ora_radial_tension_axes(ora_lattice* L, const double* center, int periodic, double rmax,
+                               int nbins, double* profile, double* phi_profile, double* Rs) {
   double* P = (double*)malloc(L->N * 6 * sizeof(double));
   double* rho = (double*)malloc(L->N * 2 * sizeof(double));
   double* sv = (double*)calloc((size_t)nbins, sizeof(double));
@@ -873,8 +882,10 @@ double ora_radial_tension(ora_lattice* L, const double* center, double rmax, int
       for (int x = 0; x < L->nx; ++x) {
         size_t i = node_at(L, x, y, z);
         if (L->solid[i]) continue;
-        double d[3] = {min_image(x - center[0], L->nx), min_image(y - center[1], L->ny),
-                       min_image(z - center[2], L->nz)};
+        double d[3] = {x - center[0], y - center[1], z - center[2]};
+        const int n[3] = {L->nx, L->ny, L->nz};
+        for (int a = 0; a < 3; ++a)
+          if ((periodic >> a) & 1) d[a] = min_image(d[a], n[a]);
         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         int b = (int)floor(sqrt(r2));
         while ((double)(b + 1) * (b + 1) <= r2) ++b;

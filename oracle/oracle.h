@@ -127,6 +127,10 @@ double ora_surface_tension_z(ora_lattice* L, double* profile);
    ((b + 1/2) / R_s)^2 profile[b], or NaN without a crossing. */
 double ora_radial_tension(ora_lattice* L, const double* center, double rmax, int nbins,
                           double* profile, double* phi_profile, double* Rs);
+/* The same with the minimum image only along the axes whose bit is set in
+   periodic (bit 0 x, bit 1 y, bit 2 z); plain differences along the others. */
+double ora_radial_tension_axes(ora_lattice* L, const double* center, int periodic, double rmax,
+                               int nbins, double* profile, double* phi_profile, double* Rs);
 
 /* Eq. (young) in degrees from the three tensions (liquid = droplet
    species), clamped to [0, 180]. */

@@ -77,6 +77,8 @@ _PROTOS = {
     "scd_pressure_tensor": [_VP, _VP],
     "scd_radial_tension": [_VP, _VP, ctypes.POINTER(_D), _D, _I32, ctypes.POINTER(_D),
                            ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "scd_radial_tension_axes": [_VP, _VP, ctypes.POINTER(_D), _I32, _D, _I32, ctypes.POINTER(_D),
+                                ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "scd_young_angle": [_D, _D, _D],
     "scd_huang_angle": [ctypes.POINTER(ScdParams), _D, _D],
     "scd_surface_tension_z": [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)],
@@ -353,17 +355,20 @@ class Lattice:
         check(lib().scd_surface_tension_z(self.h, _ptr(scratch), ctypes.byref(g), prof))
         return g.value, list(prof)
 
-    def radial_tension(self, center, rmax, nbins, scratch=None):
+    def radial_tension(self, center, rmax, nbins, scratch=None, periodic=(True, True, True)):
         """(gamma, R_s, profile of P_N - P_T, profile of phi) about center
-        (Eq. mechRadGamma); gamma and R_s are NaN without an interface."""
+        (Eq. mechRadGamma); gamma and R_s are NaN without an interface.
+        periodic: per axis (x, y, z), whether distances take the minimum
+        image (False along an axis bounded by walls)."""
         if scratch is None:
             scratch = torch.empty((6,) + self.shape, dtype=torch.float64, device=self.device)
         c = (_D * 3)(*[float(v) for v in center])
         prof, pphi = (_D * nbins)(), (_D * nbins)()
         rs, g = _D(), _D()
         self._after_torch()
-        st = lib().scd_radial_tension(self.h, _ptr(scratch), c, float(rmax), int(nbins), prof, pphi,
-                                      ctypes.byref(rs), ctypes.byref(g))
+        mask = sum(1 << a for a in range(3) if periodic[a])
+        st = lib().scd_radial_tension_axes(self.h, _ptr(scratch), c, mask, float(rmax), int(nbins),
+                                           prof, pphi, ctypes.byref(rs), ctypes.byref(g))
         if st not in (SCD_OK, SCD_ENOINTERFACE):
             check(st)
         return g.value, rs.value, list(prof), list(pphi)

@@ -434,14 +434,23 @@ scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
 scd_status scd_radial_tension(scd_lattice* h, double* d_P, const double* h_center, double rmax,
                               int32_t nbins, double* h_profile, double* h_phi_profile,
                               double* h_Rs, double* h_gamma) {
+  return scd_radial_tension_axes(h, d_P, h_center, 7, rmax, nbins, h_profile, h_phi_profile, h_Rs,
+                                 h_gamma);
+}
+
+scd_status scd_radial_tension_axes(scd_lattice* h, double* d_P, const double* h_center,
+                                   int32_t periodic, double rmax, int32_t nbins,
+                                   double* h_profile, double* h_phi_profile, double* h_Rs,
+                                   double* h_gamma) {
   if (!h || !d_P || !h_center || !h_Rs || !h_gamma) return fail(SCD_EINVAL, "NULL argument");
+  if (periodic < 0 || periodic > 7) return fail(SCD_EINVAL, "periodic mask must be in [0, 7]");
   const int maxb = RED_BLOCKS * RED_STRIDE / 3;
   if (nbins < 2 || nbins > maxb) return fail(SCD_EINVAL, "nbins must be in [2, %d]", maxb);
   scd_status st = scd_pressure_tensor(h, d_P);
   if (st) return st;
   double* shells = (double*)h->wd(h->wl.partials);
   HIPCHK(launch_radial(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
-                       h_center, nbins, d_P, shells, h->stream));
+                       h_center, periodic, nbins, d_P, shells, h->stream));
   std::vector<double> sh(3 * (size_t)nbins);
   HIPCHK(hipMemcpyAsync(sh.data(), shells, sh.size() * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

@@ -74,7 +74,8 @@ hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* link
 hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
                            int nz, const PhysD& ph, void* rho, double* P, hipStream_t s);
 hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,
-                         const double* c, int nbins, double* P, double* shells, hipStream_t s);
+                         const double* c, int periodic, int nbins, double* P, double* shells,
+                         hipStream_t s);
 hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
                                 double* profile, hipStream_t s);
 hipError_t launch_stream_copy(const double* src, double* dst, size_t n, hipStream_t s);

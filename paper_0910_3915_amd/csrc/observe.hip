@@ -526,7 +526,9 @@ __global__ __launch_bounds__(256) void k_plane_tension(const uint32_t* __restric
 }
 
 // Radial decomposition about a centre c (Eq. mechRadGamma): per fluid node,
-// with d = x - c (minimum image on the periodic axes), P_N = d.P.d / |d|^2,
+// with d = x - c (minimum image along the axes whose bit is set in periodic:
+// bit 0 x, bit 1 y, bit 2 z; the plain difference along the others),
+// P_N = d.P.d / |d|^2,
 // P_T = (tr P - P_N) / 2 (the centre node itself adds 0), written over the
 // tensor's first three components: P[i] = P_N - P_T, P[N + i] = phi,
 // P[2N + i] = shell index b (b <= |d| < b + 1, from exact comparisons on
@@ -537,9 +539,10 @@ __global__ __launch_bounds__(256) void k_radial_split(const real* __restrict__ p
                                                       const uint32_t* __restrict__ links,
                                                       int nx, int ny, int nz, double cx,
                                                       double cy, double cz, int nbins,
-                                                      double* __restrict__ P) {
+                                                      int periodic, double* __restrict__ P) {
   const int N = nx * ny * nz;
-  auto image = [](double d, int n) {
+  auto image = [periodic](double d, int n, int axis) {
+    if (!((periodic >> axis) & 1)) return d;
     if (d >= 0.5 * n) d -= n;
     if (d < -0.5 * n) d += n;
     return d;
@@ -547,8 +550,8 @@ __global__ __launch_bounds__(256) void k_radial_split(const real* __restrict__ p
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     double v = 0.0, ph = 0.0, bin = -1.0;
     if (!(links[i] & SELF_SOLID)) {
-      const double d0 = image((i % nx) - cx, nx), d1 = image(((i / nx) % ny) - cy, ny);
-      const double d2 = image((i / (nx * ny)) - cz, nz);
+      const double d0 = image((i % nx) - cx, nx, 0), d1 = image(((i / nx) % ny) - cy, ny, 1);
+      const double d2 = image((i / (nx * ny)) - cz, nz, 2);
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       int b = (int)floor(sqrt(r2));
       while ((double)(b + 1) * (b + 1) <= r2) ++b;
@@ -599,15 +602,16 @@ __global__ __launch_bounds__(256) void k_radial_shells(const double* __restrict_
 }
 
 hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,
-                         const double* c, int nbins, double* P, double* shells, hipStream_t s) {
+                         const double* c, int periodic, int nbins, double* P, double* shells,
+                         hipStream_t s) {
   const size_t N = (size_t)nx * ny * nz;
   const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   if (dtype == 0)
     hipLaunchKernelGGL(k_radial_split<double>, dim3(blocks), dim3(256), 0, s, (const double*)pop,
-                       links, nx, ny, nz, c[0], c[1], c[2], nbins, P);
+                       links, nx, ny, nz, c[0], c[1], c[2], nbins, periodic, P);
   else
     hipLaunchKernelGGL(k_radial_split<float>, dim3(blocks), dim3(256), 0, s, (const float*)pop,
-                       links, nx, ny, nz, c[0], c[1], c[2], nbins, P);
+                       links, nx, ny, nz, c[0], c[1], c[2], nbins, periodic, P);
   hipLaunchKernelGGL(k_radial_shells, dim3(nbins), dim3(256), 0, s, P, (int)N, shells);
   return hipGetLastError();
 }

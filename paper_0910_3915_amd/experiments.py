@@ -51,8 +51,25 @@ def timed_steps(L, steps, stream, chunk=1000):
     return time.perf_counter() - t0
 
 
-def sweep(dtype="f64", steps=20000, box="full", deltas=W.THROUGHPUT_DELTAS):
-    """Contact angle against the wall asymmetry rho_wall_A - rho_wall_B."""
+def sessile_radial_tension(L, ca, cfg):
+    """Eq. mechRadGamma on a sessile droplet: shells about the centre of the
+    sphere of its E1 cap, on the droplet's axis column at height
+    k_ref + H - R (the cap's sphere, R = (a_ref^2 + H^2) / 2H measured from
+    the reference layer), out to 5 lattice units before the nearest
+    border.  z distances are plain differences (the box is bounded by walls
+    in z; x and y stay periodic).  Returns (gamma, R_s, centre)."""
+    nz, ny, nx = L.shape
+    k_ref = cfg["z_solid_top"] + cfg["offset"]
+    zc = k_ref + ca["H_e1"] - ca["R_e1"]
+    centre = [float(cfg["ic"]), float(cfg["jc"]), float(zc)]
+    rmax = min(nx / 2.0, ny / 2.0, (nz - 1) - zc) - 5.0
+    g, rs, _, _ = L.radial_tension(centre, rmax, int(rmax) + 2, periodic=(True, True, False))
+    return g, rs, centre
+
+
+def sweep(dtype="f64", steps=20000, box="full", deltas=W.THROUGHPUT_DELTAS, radial=False):
+    """Contact angle against the wall asymmetry rho_wall_A - rho_wall_B; with
+    radial, also the radial surface tension of each sessile droplet."""
     stream = torch.cuda.Stream()
     out = []
     for d in deltas:
@@ -64,9 +81,14 @@ def sweep(dtype="f64", steps=20000, box="full", deltas=W.THROUGHPUT_DELTAS):
         sec = timed_steps(L, steps, stream)
         ca = L.contact_angle(c["ca"])
         obs = L.observables()
-        out.append(emit({"exp": "sweep", "box": box, "dtype": dtype, "delta": float(d), "steps": steps,
-                         "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
-                         "mlups": fluid_nodes(c["solid"]) * steps / sec / 1e6, "mass": list(obs["mass"])}))
+        row = {"exp": "sweep", "box": box, "dtype": dtype, "delta": float(d), "steps": steps,
+               "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
+               "mlups": fluid_nodes(c["solid"]) * steps / sec / 1e6, "mass": list(obs["mass"])}
+        if radial:
+            g, rs, centre = sessile_radial_tension(L, ca, c["ca"])
+            row.update({"gamma_radial": g, "R_s": rs, "R_e1": ca["R_e1"], "centre": centre})
+        out.append(emit(row))
+        del L
     return {"sweep": out}
 
 
@@ -164,7 +186,7 @@ def _planar_batch(cases, steps, stream, checkpoints=(0.5, 1.0)):
     return B_, out, sec
 
 
-def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
+def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True, with_grid=True):
     """Contact angles from planar surface tensions (Sec. 4.1, Eq. gammaMechDef
     and Eq. young) and Huang's estimate (Eq. huangSigmaLG), against the
     geometric angle.
@@ -176,7 +198,9 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
     densities of the relaxed lamella; the geometric E1/E2 angles of the
     128 x 128 x 64 droplets after 20000 steps.
     The radial tension of a free droplet (64^3, initial radius 16) gives a
-    second Young angle with the same wall tensions.
+    second Young angle with the same wall tensions, and the radial tension
+    of each sessile droplet itself (shells about its cap's sphere centre) a
+    third, compared with its geometric angle as in Sec. 4.1.
     Part 2, the paper's grid: g = 0.00 .. 0.20 (step 0.02) against the wall
     density eta = 0.00 .. 0.60 (step 0.02) with wall content (0, eta), all
     693 planar systems in one batch.  Young's angle where an A-B interface
@@ -212,7 +236,7 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
     del fd
     geo = {}
     if with_droplets:
-        for r in sweep(dtype, 20000, "full", deltas)["sweep"]:
+        for r in sweep(dtype, 20000, "full", deltas, radial=True)["sweep"]:
             geo[r["delta"]] = r
     rows = []
     for j, d in enumerate(deltas):
@@ -226,8 +250,17 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True):
         if d in geo:
             row["theta_e1"] = geo[d]["theta_e1"]
             row["theta_e2"] = geo[d]["theta_e2"]
+            gs_ = geo[d]["gamma_radial"]
+            row["gamma_AB_sessile"] = gs_
+            row["R_s_sessile"] = geo[d]["R_s"]
+            if gs_ == gs_:  # not NaN
+                th = B.young_angle(gBw, gAw, gs_)
+                row["theta_young_sessile"] = th
+                row["deviation_percent"] = 100.0 * (th - geo[d]["theta_e1"]) / geo[d]["theta_e1"]
         rows.append(emit(row))
     res["g012"] = rows
+    if not with_grid:
+        return res
     # ---- part 2
     gs = [round(0.02 * i, 2) for i in range(11)]
     etas = [round(0.02 * i, 2) for i in range(31)]
@@ -404,6 +437,7 @@ def main():
     ap.add_argument("--sweep-box", default="full")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
+    ap.add_argument("--no-grid", action="store_true", help="young: skip the 693-system grid")
     a = ap.parse_args()
     if a.what == "sweep":
         sweep(a.dtype or "f64", a.steps or 20000, a.sweep_box)
@@ -417,7 +451,7 @@ def main():
             boxes = tuple((b[0], a.steps) for b in boxes)
         sizes(a.dtype or "f32", boxes=boxes)
     elif a.what == "young":
-        young(a.dtype or "f64", a.steps or 20000)
+        young(a.dtype or "f64", a.steps or 20000, with_grid=not a.no_grid)
     elif a.what == "adjoint":
         adjoint_cost()
     else:

@@ -73,14 +73,14 @@ def _free_droplet(n=40, r0=8.0, g=0.1):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["free", "sessile", "none"])
+@pytest.mark.parametrize("name", ["free", "sessile", "sessile_open_z", "none"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_radial_tension_matches_oracle(name, dtype):
     announce(f"radial tension parity: {name} {dtype}")
     if name == "free":
         p, solid, ra, rb = _free_droplet()
         center = [20.0, 20.0, 20.0]
-    elif name == "sessile":
+    elif name in ("sessile", "sessile_open_z"):
         p, solid, ra, rb = _droplet()
         center = [12.0, 10.0, 0.5]
     else:
@@ -94,10 +94,11 @@ def test_radial_tension_matches_oracle(name, dtype):
     L.step(300)
     nb = min(p["nx"], p["ny"], p["nz"]) // 2
     rmax = nb - 5
-    g, rs, prof, pphi = L.radial_tension(center, rmax, nb)
+    per = (True, True, name != "sessile_open_z")
+    g, rs, prof, pphi = L.radial_tension(center, rmax, nb, periodic=per)
     Lo = O.Lattice(dict(p, dtype="f64"), solid)
     Lo.set_state(gpu_state_as_oracle(L))
-    go, rso, profo, pphio = Lo.radial_tension(center, rmax, nb)
+    go, rso, profo, pphio = Lo.radial_tension(center, rmax, nb, periodic=per)
     if name == "none":
         assert np.isnan(g) and np.isnan(rs) and np.isnan(go) and np.isnan(rso)
         return

@@ -129,6 +129,32 @@ def test_radial_tension_uniform_state(ora):
     assert np.allclose(prof, 0.0, atol=1e-14) and np.allclose(pphi, 0.2, atol=1e-14)
 
 
+def test_radial_tension_open_axis_equals_padded_box(ora):
+    """A sessile droplet between walls at z = 0 and nz - 1: its radial
+    profile with the plain z distance equals the fully periodic profile of
+    the same state in a box of twice the height whose added layers are all
+    wall, where no shell can wrap across z.  With the minimum image in z the
+    original box wraps the upper nodes onto the inner shells, so that
+    profile differs."""
+    c = W.droplet_case(16, 16, 12, 5.0, 0.1, 0.2)
+    L = ora.Lattice(c["params"], c["solid"])
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    L.step(40)
+    s = L.get_state()
+    nz = 12
+    p2 = dict(c["params"], nz=2 * nz)
+    solid2 = np.concatenate([c["solid"], np.ones_like(c["solid"])], axis=0)
+    L2 = ora.Lattice(p2, solid2)
+    L2.set_state(np.concatenate([s, np.zeros_like(s)], axis=0))
+    centre = [8.0, 8.0, 0.5]
+    g_open, rs_open, prof_open, phi_open = L.radial_tension(centre, 7.0, 8, periodic=(True, True, False))
+    g_pad, rs_pad, prof_pad, phi_pad = L2.radial_tension(centre, 7.0, 8)
+    assert np.array_equal(prof_open, prof_pad) and np.array_equal(phi_open, phi_pad)
+    assert (np.isnan(g_open) and np.isnan(g_pad)) or g_open == g_pad
+    _, _, prof_wrap, _ = L.radial_tension(centre, 7.0, 8)
+    assert not np.allclose(prof_wrap, prof_open, rtol=0, atol=1e-6)
+
+
 @pytest.mark.slow
 def test_radial_tension_free_droplet(ora):
     """A relaxed free droplet: the radial mechanical-equilibrium identity
