@@ -169,14 +169,23 @@ __device__ double col_crossing(const CaGeom& g, const double* col, const double*
   return __builtin_nan("");
 }
 
+// Half-chord along (sx, sy) from the droplet axis: the first crossing
+// > 0 -> <= 0 of phi between neighbouring nodes of the ray, which steps
+// periodically (the coordinates advance by one with wrap-around, no modulo).
 __device__ double layer_ray(const CaGeom& g, const LayerRC& layer, int sx, int sy, int* flags) {
   const int len = sx != 0 ? g.nx : g.ny;
+  int x = wrap_index(g.c.ic, g.nx), y = wrap_index(g.c.jc, g.ny);
+  double p0 = layer.at(x, y);
   for (int m = 0; m < len / 2; ++m) {
-    const int x0 = wrap_index(g.c.ic + m * sx, g.nx), y0 = wrap_index(g.c.jc + m * sy, g.ny);
-    const int x1 = wrap_index(g.c.ic + (m + 1) * sx, g.nx);
-    const int y1 = wrap_index(g.c.jc + (m + 1) * sy, g.ny);
-    const double p0 = layer.at(x0, y0), p1 = layer.at(x1, y1);
+    x += sx;
+    y += sy;
+    if (x == g.nx) x = 0;
+    if (x < 0) x = g.nx - 1;
+    if (y == g.ny) y = 0;
+    if (y < 0) y = g.ny - 1;
+    const double p1 = layer.at(x, y);
     if (p0 > 0.0 && p1 <= 0.0) return m + p0 / (p0 - p1);
+    p0 = p1;
   }
   *flags |= 8;  // SCD_CA_RAY_LIMIT
   return (double)(len / 2);
@@ -264,14 +273,36 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
   }
   __syncthreads();
   const LayerRC refRC{rowR, colR, c.jc}, lowRC{rowL, colL, c.jc};
-  // layer sums: sum chi inside the E2 window, centroid of phi > 0
-  const double rcut = e2_window(g, refRC);
+  // layer sums: sum chi inside the E2 window, centroid of phi > 0; the
+  // window comes from a serial scan, done once and shared through LDS
+  if (threadIdx.x == 0) sh[0] = e2_window(g, refRC);
+  __syncthreads();
+  const double rcut = sh[0];
+  __syncthreads();
+  // One workgroup walks the whole layer, so each thread requests the link
+  // masks and phi of UNR of its nodes before using any: one memory round
+  // trip per UNR nodes.  The nodes are summed in the same order as one by one.
   double v[4] = {0, 0, 0, 0};
-  for (int t = threadIdx.x; t < A; t += blockDim.x) {
-    const int x = t % nx, y = t / nx;
-    if (g.solid(x, y, kref)) continue;
-    if (in_window(g, rcut, x, y)) v[0] += smoothstep((ref[t] + c.eps) / (2.0 * c.eps));
-    if (ref[t] > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
+  constexpr int UNR = 8;
+  const bool layer_in = kref >= 0 && kref < nz;
+  const uint32_t* lref = links + (size_t)(layer_in ? kref : 0) * A;
+  for (int t0 = threadIdx.x; t0 < A; t0 += UNR * blockDim.x) {
+    uint32_t lk[UNR];
+    double pv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int t = t0 + u * blockDim.x;
+      lk[u] = (layer_in && t < A) ? lref[t] : SELF_SOLID;
+      pv[u] = t < A ? ref[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int t = t0 + u * blockDim.x;
+      if (lk[u] & SELF_SOLID) continue;
+      const int y = t / nx, x = t - y * nx;
+      if (in_window(g, rcut, x, y)) v[0] += smoothstep((pv[u] + c.eps) / (2.0 * c.eps));
+      if (pv[u] > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
+    }
   }
   block_sum<4>(v, sh);
   if (threadIdx.x != 0) return;

@@ -108,3 +108,20 @@ def test_radial_tension_matches_oracle(name, dtype):
     assert np.allclose(pphi, pphio, rtol=0, atol=tol)
     assert abs(rs - rso) < 1e3 * tol
     assert abs(g - go) <= 1e3 * tol * abs(go)
+
+
+@pytest.mark.gpu
+def test_radial_tension_axes_rejects_bad_mask():
+    import ctypes
+    announce("radial tension: periodic mask outside [0, 7]")
+    p, solid, ra, rb = _free_droplet(16, 4.0)
+    L = scd.Lattice(p, solid)
+    L.init_equilibrium(ra, rb)
+    scratch = torch.empty((6,) + L.shape, dtype=torch.float64, device="cuda")
+    c = (ctypes.c_double * 3)(8.0, 8.0, 8.0)
+    rs, g = ctypes.c_double(), ctypes.c_double()
+    lib = scd.binding.lib()
+    for mask in (-1, 8):
+        st = lib.scd_radial_tension_axes(L.h, ctypes.c_void_p(scratch.data_ptr()), c, mask, 3.0, 8,
+                                         None, None, ctypes.byref(rs), ctypes.byref(g))
+        assert st == scd.binding.SCD_EINVAL, mask
