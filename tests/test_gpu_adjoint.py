@@ -86,6 +86,34 @@ def test_checkpointed_gradient_matches_oracle_and_fd():
         assert abs(fd - g[i]) <= 1e-6 * max(abs(fd), abs(g[i])), (i, fd, g[i])
 
 
+def test_gradient_workload_full_size_matches_finite_differences():
+    """The gradient workload at its own size (64 x 64 x 48, cap radius 14,
+    2000 steps, checkpoints every 100, moment cache on): the checkpointed
+    gradient of (theta_E2 - 120)^2 with respect to the five wall and
+    coupling parameters against central differences of the GPU forward
+    pass (the oracle would need every state of the run at this size)."""
+    c = W.config_gradient()
+    announce("gradient: 64x64x48, 2000 steps, K=100, against central differences")
+    setup = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], 2000, 100, c["ca"], 120.0)
+    p = c["params"]
+    v0 = np.array([p["rho_wall"][0], p["rho_wall"][1], p["g_ab"], p["g_wall"][0], p["g_wall"][1]])
+    setup.apply_params(v0)
+    setup.forward()
+    g = np.array(setup.backward())
+    assert np.all(np.isfinite(g)) and np.max(np.abs(g)) > 0
+    h = 1e-5
+    for i in range(5):
+        vp, vm = v0.copy(), v0.copy()
+        vp[i] += h
+        vm[i] -= h
+        setup.apply_params(vp)
+        fp = setup.forward()
+        setup.apply_params(vm)
+        fm = setup.forward()
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-4 * np.max(np.abs(g)), (i, fd, g[i])
+
+
 def test_two_level_checkpoints_match_one_level():
     c = _tiny(-0.1)
     nsteps, target = 60, 110.0
