@@ -85,3 +85,44 @@ def test_batch_autotune_then_default_tiles_match_sequential(tmp_path):
         L.init_equilibrium(c["rho_a"], c["rho_b"])
         L.step(24)
         assert torch.equal(B.view(i).get_state().cpu(), L.get_state().cpu()), i
+
+
+def test_full_batch_sweep_equals_sequential():
+    """The 64-droplet FP32 sweep the bench times (42 M nodes, boxes of
+    64-128 x 64-128 x 48-96), in the bench's launch configuration (batch
+    autotuner, re-initialised, a captured graph of 20 steps): every member
+    equals the same droplet stepped alone with the tile the autotuner chose,
+    bit for bit, and the library's default tile up to FP32 rounding (the
+    variants order the force sum differently)."""
+    announce("batch: the 64-droplet FP32 sweep, autotuned, 20 steps in a graph, vs one by one")
+    draws = W.batch_draw(64, seed=0)
+    cases = [W.droplet_case(d["nx"], d["ny"], d["nz"], d["radius"], d["g_ab"], d["delta"], dtype="f32")
+             for d in draws]
+    s = torch.cuda.Stream()
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    best, _ = B.autotune(3, None)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    B.graph_capture(20)
+    B.graph_replay(1)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, c in enumerate(cases):
+        v = B.view(i)
+        assert v.step_count == 20, i
+        got = v.get_state()
+        L = scd.Lattice(c["params"], c["solid"], stream=s)
+        L.set_tile(best[0], min(best[1], c["params"]["nz"]))
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(20)
+        assert torch.equal(got, L.get_state()), i
+        L.close()
+        D = scd.Lattice(c["params"], c["solid"], stream=s)
+        D.init_equilibrium(c["rho_a"], c["rho_b"])
+        D.step(20)
+        worst = max(worst, torch.max(torch.abs(got - D.get_state())).item())
+        D.close()
+    announce(f"batch: largest difference from the default tile {worst:.3e}")
+    assert worst <= 1e-5
