@@ -8,7 +8,7 @@ import torch
 import oracle as O
 import paper_0910_3915_amd as scd
 import workloads as W
-from gpu_helpers import announce, gpu_state_as_oracle
+from gpu_helpers import announce
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,8 @@ def test_seed_matches_oracle():
     L.step(30)
     lam = O.from_gpu_layout(L.ca_seed(c["ca"], 2.5).cpu().numpy())
     Lo = O.Lattice(c["params"], c["solid"])
-    Lo.set_state(gpu_state_as_oracle(L))
+    Lo.init_equilibrium(c["rho_a"], c["rho_b"])
+    Lo.step(30)
     lo, rc = Lo.ca_seed(c["ca"], 2.5)
     assert rc == 0
     assert np.max(np.abs(lam - lo)) <= 1e-9 * np.max(np.abs(lo))
@@ -52,7 +53,9 @@ def test_adjoint_step_matches_oracle(variant):
     lam_t = torch.from_numpy(lam).cuda()
     out, dp = L.adjoint_step(st, lam_t)
     Lo = O.Lattice(p, solid)
-    lo, dpo = Lo.adjoint_step(O.from_gpu_layout(st.cpu().numpy()), O.from_gpu_layout(lam))
+    Lo.init_equilibrium(ra, rb)
+    Lo.step(5)
+    lo, dpo = Lo.adjoint_step(Lo.get_state(), O.from_gpu_layout(lam))
     g = O.from_gpu_layout(out.cpu().numpy())
     assert np.max(np.abs(g - lo)) <= 1e-11 * np.max(np.abs(lo))
     assert np.allclose(dp, dpo, rtol=1e-10, atol=1e-10 * np.max(np.abs(dpo)))
@@ -131,12 +134,12 @@ def test_gradient_from_current_state_matches_oracle():
     L = scd.Lattice(c["params"], c["solid"], adjoint=True)
     L.init_equilibrium(c["rho_a"], c["rho_b"])
     L.step(20)
-    s20 = O.from_gpu_layout(L.get_state().cpu().numpy())
     setup = scd.GradSetup(c["params"], c["solid"], None, None, 30, 8, c["ca"], 100.0, lattice=L, inner=3)
     loss = setup.forward()
     g = setup.backward()
     Lo = O.Lattice(c["params"], c["solid"])
-    Lo.set_state(s20)
+    Lo.init_equilibrium(c["rho_a"], c["rho_b"])
+    Lo.step(20)
     states = []
     for _ in range(30):
         states.append(Lo.get_state())
