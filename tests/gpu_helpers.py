@@ -11,6 +11,8 @@ def gpu_density(L):
 
 
 def gpu_state_as_oracle(L):
+    """A GPU lattice's state in the oracle's array order, to compare with an
+    oracle result (never to feed the oracle)."""
     return O.from_gpu_layout(L.get_state().double().cpu().numpy())
 
 
