@@ -209,9 +209,10 @@ class Lattice:
         self.pop_bytes = pop_b.value
         self.dtype = _torch_dtype(self.sp)
         self.solid = torch.as_tensor(solid, dtype=torch.uint8).reshape(self.shape).to(self.device).contiguous()
-        # population buffers in the library's blocked layout (flat)
+        # population buffers in the library's blocked layout (flat); zeroed so
+        # that the padding slots, which nothing writes, hold zeros
         self.pop_numel = self.pop_bytes // torch.empty((), dtype=self.dtype).element_size()
-        self.pop = [torch.empty(self.pop_numel, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.pop = [torch.zeros(self.pop_numel, dtype=self.dtype, device=self.device) for _ in range(2)]
         self.work = _alloc_bytes(work_b.value, self.device)
         self.stream = stream
         h = ctypes.c_void_p()
@@ -266,7 +267,10 @@ class Lattice:
     # elements), which the C calls read and write.  pack/unpack convert on
     # the lattice's stream.
     def empty_blocked(self):
-        return torch.empty(self.pop_numel, dtype=self.dtype, device=self.device)
+        """A blocked population tensor, zeroed: the library writes only the
+        node slots, so its padding slots stay zero and whole buffers compare
+        and copy deterministically."""
+        return torch.zeros(self.pop_numel, dtype=self.dtype, device=self.device)
 
     def pack(self, plain, out=None):
         plain = plain.to(device=self.device, dtype=self.dtype).contiguous()
@@ -405,7 +409,7 @@ class Lattice:
         Population tensors are plain unless blocked=True."""
         if blocked:
             st, li = state_t, lam_in
-            lo = torch.empty_like(lam_in) if lam_out is None else lam_out
+            lo = torch.zeros_like(lam_in) if lam_out is None else lam_out
         else:
             st, li, lo = self.pack(state_t), self.pack(lam_in), self.empty_blocked()
         self._after_torch()
@@ -489,7 +493,7 @@ class Batch:
         arr = (ScdParams * n)(*[make_params(p) for p in params_list])
         nbytes = ctypes.c_size_t()
         check(lib().scd_batch_sizes(n, arr, ctypes.byref(nbytes)))
-        self.arena = _alloc_bytes(nbytes.value, self.device)
+        self.arena = _alloc_bytes(nbytes.value, self.device).zero_()  # padding slots stay zero
         self.solids = [torch.as_tensor(s, dtype=torch.uint8).to(self.device).contiguous() for s in solids]
         ptrs = (ctypes.c_void_p * n)(*[s.data_ptr() for s in self.solids])
         self.stream = stream
