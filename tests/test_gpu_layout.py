@@ -59,3 +59,22 @@ def test_pack_rejects_overlap():
     q = ctypes.c_void_p(buf.data_ptr() + 8 * 64)
     assert B.lib().scd_pop_pack(L.h, p, q) == B.SCD_EINVAL
     assert B.lib().scd_pop_unpack(L.h, p, None) == B.SCD_EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_padding_slots_stay_zero(dtype):
+    """On a box whose planes are not a whole number of blocks, the padding
+    slots of the state the binding hands out are zero after stepping: the
+    kernels write node slots only."""
+    import workloads as W
+    announce(f"pop padding after 10 steps: 20x18x14 droplet, {dtype}")
+    c = W.droplet_case(20, 18, 14, 5.0, 0.12, 0.2, dtype=dtype)
+    L = scd.Lattice(c["params"], c["solid"])
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    L.step(10)
+    idx, total = blocked_index(20, 18, 14)
+    node = np.zeros(total, bool)
+    node[idx.reshape(-1)] = True
+    st = L.get_state(blocked=True).cpu().numpy()
+    assert not node.all()
+    assert np.all(st[~node] == 0)
