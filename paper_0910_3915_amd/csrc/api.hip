@@ -526,7 +526,8 @@ scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out)
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
   HIPCHK(launch_contact_angle(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
-                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.ca), h->stream));
+                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.partials),
+                              h->wd(h->wl.ca), h->stream));
   double status;
   st = read_ca(h, out, &status);
   if (st) return st;
@@ -539,7 +540,8 @@ scd_status scd_ca_seed(scd_lattice* h, const scd_ca_cfg* cfg, double dL_dtheta, 
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
   HIPCHK(launch_contact_angle(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
-                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.ca), h->stream));
+                              ca_dev(cfg), h->wd(h->wl.phi), h->wd(h->wl.partials),
+                              h->wd(h->wl.ca), h->stream));
   HIPCHK(launch_ca_seed(h->p.dtype, h->links(), h->p.nx, h->p.ny, h->p.nz, ca_dev(cfg),
                         h->wd(h->wl.phi), h->wd(h->wl.ca), dL_dtheta, d_lambda, h->stream));
   scd_ca ca;

@@ -69,8 +69,8 @@ struct CaDev {
   double eps;
 };
 hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
-                                int nz, CaDev cfg, double* phi_scratch, double* result,
-                                hipStream_t s);
+                                int nz, CaDev cfg, double* phi_scratch, double* partials,
+                                double* result, hipStream_t s);
 hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
                            int nz, const PhysD& ph, void* rho, double* P, hipStream_t s);
 hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,

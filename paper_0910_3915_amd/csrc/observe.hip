@@ -242,11 +242,55 @@ __device__ __forceinline__ bool in_window(const CaGeom& g, double rcut, int x, i
   return dx * dx + dy * dy <= rcut * rcut;
 }
 
+// Layer sums of the reference layer (sum of chi inside the E2 window; sum of
+// x, y and count where phi > 0), split over CA_LAYER_BLOCKS workgroups with
+// one node per thread.  Each workgroup stages the layer's row and column
+// through the droplet axis and finds the E2 window itself, then writes its
+// four partial sums to part; workgroup 0 also writes the window radius to
+// part[4 * CA_LAYER_BLOCKS].
+constexpr int CA_LAYER_BLOCKS = 64;  // one wavefront of k_ca_finish adds them
+__global__ __launch_bounds__(256) void k_ca_layer(const uint32_t* __restrict__ links, int nx,
+                                                  int ny, int nz, CaDev c,
+                                                  const double* __restrict__ phi,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[4 * 16];
+  extern __shared__ double stage[];  // 8 * (nx + ny) bytes
+  const CaGeom g{nx, ny, nz, links, c};
+  const int A = nx * ny;
+  const int kref = c.zs + c.off;
+  const double* ref = phi;
+  double* rowR = stage;
+  double* colR = rowR + nx;
+  for (int t = threadIdx.x; t < nx; t += blockDim.x) rowR[t] = ref[c.jc * nx + t];
+  for (int t = threadIdx.x; t < ny; t += blockDim.x) colR[t] = ref[t * nx + c.ic];
+  __syncthreads();
+  const LayerRC refRC{rowR, colR, c.jc};
+  if (threadIdx.x == 0) sh[0] = e2_window(g, refRC);
+  __syncthreads();
+  const double rcut = sh[0];
+  __syncthreads();
+  double v[4] = {0, 0, 0, 0};
+  const bool layer_in = kref >= 0 && kref < nz;
+  const uint32_t* lref = links + (size_t)(layer_in ? kref : 0) * A;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A; t += gridDim.x * blockDim.x) {
+    if (!layer_in || (lref[t] & SELF_SOLID)) continue;
+    const int y = t / nx, x = t - y * nx;
+    const double p = ref[t];
+    if (in_window(g, rcut, x, y)) v[0] += smoothstep((p + c.eps) / (2.0 * c.eps));
+    if (p > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < 4; ++j) part[4 * blockIdx.x + j] = v[j];
+    if (blockIdx.x == 0) part[4 * CA_LAYER_BLOCKS] = rcut;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ links, int nx,
                                                    int ny, int nz, CaDev c,
                                                    const double* __restrict__ phi,
+                                                   const double* __restrict__ part,
                                                    double* __restrict__ res) {
-  __shared__ double sh[4 * 16];
   extern __shared__ double stage[];  // ca_stage_bytes(nx, ny, nz)
   const CaGeom g{nx, ny, nz, links, c};
   const int A = nx * ny;
@@ -273,39 +317,19 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
   }
   __syncthreads();
   const LayerRC refRC{rowR, colR, c.jc}, lowRC{rowL, colL, c.jc};
-  // layer sums: sum chi inside the E2 window, centroid of phi > 0; the
-  // window comes from a serial scan, done once and shared through LDS
-  if (threadIdx.x == 0) sh[0] = e2_window(g, refRC);
-  __syncthreads();
-  const double rcut = sh[0];
-  __syncthreads();
-  // One workgroup walks the whole layer, so each thread requests the link
-  // masks and phi of UNR of its nodes before using any: one memory round
-  // trip per UNR nodes.  The nodes are summed in the same order as one by one.
+  // the layer sums of k_ca_layer: lane b of the first wave takes workgroup
+  // b's partials, and a fixed butterfly adds them
+  static_assert(CA_LAYER_BLOCKS == 64, "one partial per lane of a wavefront");
   double v[4] = {0, 0, 0, 0};
-  constexpr int UNR = 8;
-  const bool layer_in = kref >= 0 && kref < nz;
-  const uint32_t* lref = links + (size_t)(layer_in ? kref : 0) * A;
-  for (int t0 = threadIdx.x; t0 < A; t0 += UNR * blockDim.x) {
-    uint32_t lk[UNR];
-    double pv[UNR];
+  if (threadIdx.x < 64) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int t = t0 + u * blockDim.x;
-      lk[u] = (layer_in && t < A) ? lref[t] : SELF_SOLID;
-      pv[u] = t < A ? ref[t] : 0.0;
-    }
+    for (int j = 0; j < 4; ++j) v[j] = part[4 * threadIdx.x + j];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int t = t0 + u * blockDim.x;
-      if (lk[u] & SELF_SOLID) continue;
-      const int y = t / nx, x = t - y * nx;
-      if (in_window(g, rcut, x, y)) v[0] += smoothstep((pv[u] + c.eps) / (2.0 * c.eps));
-      if (pv[u] > 0.0) { v[1] += x; v[2] += y; v[3] += 1.0; }
-    }
+    for (int j = 0; j < 4; ++j)
+      for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
   }
-  block_sum<4>(v, sh);
   if (threadIdx.x != 0) return;
+  const double rcut = part[4 * CA_LAYER_BLOCKS];
 
   const double nan = __builtin_nan("");
   int flags = 0;
@@ -391,8 +415,8 @@ __global__ __launch_bounds__(256) void k_ca_finish(const uint32_t* __restrict__ 
 }
 
 hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* links, int nx, int ny,
-                                int nz, CaDev cfg, double* phi_scratch, double* result,
-                                hipStream_t s) {
+                                int nz, CaDev cfg, double* phi_scratch, double* partials,
+                                double* result, hipStream_t s) {
   const int total = 2 * nx * ny + nz;
   const int blocks = (total + 255) / 256;
   if (dtype == 0)
@@ -407,8 +431,16 @@ hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* link
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage);
     if (e != hipSuccess) return e;
   }
+  const size_t lstage = (size_t)8 * ((size_t)nx + (size_t)ny);
+  if (lstage > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ca_layer,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lstage);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ca_layer, dim3(CA_LAYER_BLOCKS), dim3(256), lstage, s, links, nx, ny, nz,
+                     cfg, phi_scratch, partials);
   hipLaunchKernelGGL(k_ca_finish, dim3(1), dim3(256), stage, s, links, nx, ny, nz, cfg,
-                     phi_scratch, result);
+                     phi_scratch, partials, result);
   return hipGetLastError();
 }
 
