@@ -350,10 +350,14 @@ scd_status scd_batch_destroy(scd_batch* b);
 scd_status scd_batch_lattice(scd_batch* b, int32_t i, scd_lattice** view);
 scd_status scd_batch_init_equilibrium(scd_batch* b, int32_t i, const double* d_rho_a,
                                       const double* d_rho_b);
-/* Step variant (see scd_tile_list), z-chunk and number of persistent
- * workgroups (grid); grid 0 (the default) launches one workgroup per
- * (lattice, tile) item.  Defaults: FP32 64x4 one-node-per-thread tiles,
- * FP64 the single-lattice default variant; 32-plane chunks. */
+/* Step variant (see scd_tile_list), z-chunk (1 .. 32767 planes, else
+ * SCD_EINVAL) and number of persistent workgroups (grid); grid 0 (the
+ * default) launches one workgroup per (lattice, tile) item, a shorter grid
+ * walks the items persistently (rounded up to a multiple of 8).  Items are
+ * dealt to the 8 XCDs in contiguous ranges (the chunks of a tile column and
+ * the columns of a lattice stay on one XCD), and neighbouring z-chunks march
+ * in opposite directions, as in scd_step.  Defaults: the single-lattice
+ * default variant of the dtype, 32-plane chunks, grid 0. */
 scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t grid);
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps);

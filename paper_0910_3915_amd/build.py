@@ -1,7 +1,13 @@
-"""Build libscdrop.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libscdrop.so (HIP, gfx950) in-tree with hipcc.
+
+Each source is compiled to its own object in parallel (the kernels of one
+file call no device code of another), then the objects are linked into the
+shared library.
+"""
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -14,7 +20,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -24,11 +29,23 @@ HIPCC_FLAGS = [
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="scdrop_build_") as tmp:
+        objs, procs = [], []
+        for s in SOURCES:
+            o = os.path.join(tmp, os.path.splitext(s)[0] + ".o")
+            cmd = [hipcc] + HIPCC_FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((s, subprocess.Popen(cmd)))
+            objs.append(o)
+        failed = [s for s, p in procs if p.wait() != 0]
+        if failed:
+            raise RuntimeError("hipcc failed on " + ", ".join(failed))
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

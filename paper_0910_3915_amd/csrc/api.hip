@@ -961,6 +961,7 @@ struct scd_batch {
   size_t items_off;
   int nitems;
   int variant, zc, grid;
+  int remap;  // XCD-contiguous ranges of the work list
   hipStream_t stream;
   int parity;
   hipGraph_t graph;
@@ -1021,17 +1022,24 @@ scd_status batch_upload(scd_batch* b) {
     latdev_fill(b->dtype, d1.data() + ds * i, v->pop[1], v->pop[0], v->links(), v->p.nx, v->p.ny,
                 v->p.nz, v->ph);
     const int zc = std::min(b->zc, v->p.nz);
+    if (zc > 32767) return fail(SCD_EINVAL, "z-chunk %d exceeds 32767 planes", zc);
     int tx, ty, var, wpe;
     variant_at(b->variant, &tx, &ty, &var, &wpe);
     const int gx = (v->p.nx + tx - 1) / tx, gy = (v->p.ny + ty - 1) / ty;
     const int gz = (v->p.nz + zc - 1) / zc;
-    for (int bz = 0; bz < gz; ++bz)
-      for (int by = 0; by < gy; ++by)
-        for (int bx = 0; bx < gx; ++bx) {
+    // chunks of a column adjacent, then the columns along x, then y; even
+    // chunks march down and odd ones up, so that two neighbouring chunks
+    // reach their shared boundary planes together (as in the single-lattice
+    // step)
+    for (int by = 0; by < gy; ++by)
+      for (int bx = 0; bx < gx; ++bx)
+        for (int bz = 0; bz < gz; ++bz) {
+          const int za = bz * zc, zlen = std::min(zc, v->p.nz - za);
+          const bool down = !(bz & 1) && gz > 1;
           items.push_back(i);
           items.push_back(bx);
           items.push_back(by);
-          items.push_back((zc << 16) | (bz * zc));
+          items.push_back((int32_t)((uint32_t)za | ((uint32_t)zlen << 16) | (down ? 0x80000000u : 0u)));
         }
   }
   b->nitems = (int)(items.size() / 4);
@@ -1045,10 +1053,11 @@ scd_status batch_upload(scd_batch* b) {
 
 // Default batch tile: with many (lattice, tile) items the z-halo re-reads of
 // short chunks cost more than the lost parallelism of long ones, so the
-// batch marches 32 planes per item; one workgroup per item (grid 0).
+// batch marches 32 planes per item with the single-lattice default variant;
+// one workgroup per item (grid 0), items dealt to the XCDs in contiguous
+// ranges.
 void batch_default_tile(int dtype, int* variant, int* zc, int* grid) {
-  *variant = variant_find(64, 4, 0, 1);
-  if (*variant < 0) *variant = default_variant(dtype);
+  *variant = default_variant(dtype);
   *zc = 32;
   *grid = 0;
 }
@@ -1063,9 +1072,13 @@ void batch_drop_graph(scd_batch* b) {
 
 scd_status batch_enqueue(scd_batch* b, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
-    const int grid = (b->grid <= 0 || b->grid > b->nitems) ? b->nitems : b->grid;
+    // one workgroup per item, or a persistent grid (a multiple of 8 with
+    // the XCD remap, so that each block stays on one XCD's range)
+    const int slots = b->remap ? 8 * ((b->nitems + 7) / 8) : b->nitems;
+    int grid = (b->grid <= 0 || b->grid > slots) ? slots : b->grid;
+    if (b->remap) grid = 8 * ((grid + 7) / 8);
     HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity], b->arena + b->items_off,
-                             b->nitems, grid, b->variant, b->stream));
+                             b->nitems, grid, b->variant, b->remap, b->stream));
     b->parity ^= 1;
     for (scd_lattice* v : b->views) {
       v->cur = b->parity;
@@ -1106,6 +1119,7 @@ scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const
   b->desc_off[1] = L.desc[1];
   b->items_off = L.items;
   batch_default_tile(p[0].dtype, &b->variant, &b->zc, &b->grid);
+  b->remap = 1;
   b->stream = (hipStream_t)stream;
   b->parity = 0;
   b->graph = nullptr;
@@ -1160,7 +1174,8 @@ scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t
   if (!b) return fail(SCD_EINVAL, "NULL handle");
   if (variant < 0 || variant >= variant_count())
     return fail(SCD_EINVAL, "variant %d is not compiled", variant);
-  if (zc < 1 || grid < 0) return fail(SCD_EINVAL, "z-chunk must be >= 1 and grid >= 0");
+  if (zc < 1 || zc > 32767 || grid < 0)
+    return fail(SCD_EINVAL, "z-chunk must be in [1, 32767] and grid >= 0");
   b->variant = variant;
   b->zc = zc;
   b->grid = grid;

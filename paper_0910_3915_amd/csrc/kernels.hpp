@@ -48,8 +48,10 @@ hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* li
                        int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
                        hipStream_t s, void* mom_out = nullptr);
 bool variant_writes_moments(int variant);
+// items: int4 {lattice, bx, by, zw} (zw: first plane | chunk length << 16
+// | downward << 31); grid workgroups walk them (remap: XCD-contiguous ranges)
 hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
-                             int variant, hipStream_t s);
+                             int variant, int remap, hipStream_t s);
 size_t latdev_size(int dtype);
 void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_t* links, int nx,
                  int ny, int nz, const PhysD& ph);

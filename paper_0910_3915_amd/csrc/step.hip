@@ -1076,18 +1076,32 @@ void k_step(LatDev<real> L, int gx, int gy, int nchunks, int zc, int remap) {
   run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds, (bz & 1) || nchunks == 1 ? 1 : -1);
 }
 
-// Batched: a persistent grid walks a list of (lattice, tile) items.
+// Batched: the grid walks a list of (lattice, tile) items, one item per
+// workgroup at a time (a persistent grid when it is shorter than the list).
+// Item {lattice, bx, by, zw}: zw holds the first plane in bits 0-15, the
+// chunk length in bits 16-30 and the march direction in bit 31 (set: down).
+// With remap, slot s of the walk takes item (s mod 8) * per + s / 8, so that
+// each XCD (blocks are dealt to the 8 XCDs round-robin, and a persistent
+// grid is a multiple of 8) works through one contiguous range of the list,
+// in which the chunks of a column and the columns of a lattice are adjacent.
 template <typename real, int TX, int TY, int VAR, int WPE>
 __global__ __launch_bounds__((StepShape<real, TX, TY, VAR>::THREADS))
 __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_step_batch(const LatDev<real>* __restrict__ lats, const int4* __restrict__ items,
-                  int nitems) {
+                  int nitems, int remap) {
   __shared__ __align__(16) real lds[StepShape<real, TX, TY, VAR>::LDS_REALS];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int4 w = items[it];  // lattice, bx, by, (z-chunk << 16) | first plane
-    const LatDev<real> L = lats[w.x];
-    const int zc = w.w >> 16, za = w.w & 0xffff;
-    run_tile<real, TX, TY, VAR>(L, w.y, w.z, za, min(za + zc, L.nz), lds);
+  const int per = (nitems + 7) / 8;
+  const int slots = remap ? 8 * per : nitems;
+  for (int s = blockIdx.x; s < slots; s += gridDim.x) {
+    const int it = remap ? (s & 7) * per + (s >> 3) : s;
+    if (it >= nitems) continue;
+    const int4 w = items[it];
+    // the descriptor is read in place (a local copy whose address the
+    // tile's lambdas take would live in scratch memory)
+    const LatDev<real>& L = lats[w.x];
+    const uint32_t zw = (uint32_t)w.w;
+    const int za = (int)(zw & 0xffffu), zlen = (int)((zw >> 16) & 0x7fffu);
+    run_tile<real, TX, TY, VAR>(L, w.y, w.z, za, za + zlen, lds, (zw >> 31) ? -1 : 1);
     __syncthreads();  // the next item rewrites the LDS ring
   }
 }
@@ -1344,7 +1358,7 @@ bool variant_writes_moments(int variant) {
 
 template <typename real>
 static hipError_t launch_batch_t(const void* lats, const void* items, int nitems, int grid,
-                                 int variant, hipStream_t s) {
+                                 int variant, int remap, hipStream_t s) {
   if (variant < 0 || variant >= variant_count()) return hipErrorInvalidValue;
   const int tx = kVariants[variant][0], ty = kVariants[variant][1];
   const int var = kVariants[variant][2], wpe = kVariants[variant][3];
@@ -1352,7 +1366,7 @@ static hipError_t launch_batch_t(const void* lats, const void* items, int nitems
   if (tx == a && ty == b && var == v && wpe == w) {                                             \
     hipLaunchKernelGGL((k_step_batch<real, a, b, v, w>), dim3(grid),                            \
                        dim3(StepShape<real, a, b, v>::THREADS), 0, s,                           \
-                       (const LatDev<real>*)lats, (const int4*)items, nitems);                  \
+                       (const LatDev<real>*)lats, (const int4*)items, nitems, remap);           \
     return hipGetLastError();                                                                   \
   }
   SCD_VARIANTS(SCD_LAUNCHB)
@@ -1361,9 +1375,9 @@ static hipError_t launch_batch_t(const void* lats, const void* items, int nitems
 }
 
 hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
-                             int variant, hipStream_t s) {
-  if (dtype == 0) return launch_batch_t<double>(lats, items, nitems, grid, variant, s);
-  return launch_batch_t<float>(lats, items, nitems, grid, variant, s);
+                             int variant, int remap, hipStream_t s) {
+  if (dtype == 0) return launch_batch_t<double>(lats, items, nitems, grid, variant, remap, s);
+  return launch_batch_t<float>(lats, items, nitems, grid, variant, remap, s);
 }
 
 size_t latdev_size(int dtype) { return dtype == 0 ? sizeof(LatDev<double>) : sizeof(LatDev<float>); }

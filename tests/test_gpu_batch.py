@@ -1,13 +1,16 @@
 """Batched persistent launch: members of uneven sizes and parameters must
 evolve bitwise as the same lattices stepped one by one, with and without a
-captured HIP graph; the autotuner must keep results unchanged."""
+captured HIP graph; the autotuner must keep results unchanged; and every
+member, stepped in the batch, must match the oracle's own run of it (FP64 to
+1e-12, FP32 within the rounding of a few tens of steps, the bound of the
+full-size FP32 parity test)."""
 import numpy as np
 import pytest
 import torch
 
 import paper_0910_3915_amd as scd
 import workloads as W
-from gpu_helpers import announce
+from gpu_helpers import announce, gpu_state_as_oracle, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +47,30 @@ def test_batch_equals_sequential(dtype, grid):
         assert torch.equal(v.get_state().cpu(), L.get_state().cpu()), i
         a, b = v.contact_angle(c["ca"]), L.contact_angle(c["ca"])
         assert a["theta_e1"] == b["theta_e1"] or (np.isnan(a["theta_e1"]) and np.isnan(b["theta_e1"]))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_members_against_oracle(dtype):
+    """Three uneven members (one of them with a 64-wide tile's worth of idle
+    lanes) stepped 40 times in the batch with its default tile (20 eager
+    steps, then a captured graph of 10 replayed twice) against the oracle's
+    run of each member from the same seeded densities, every population."""
+    announce(f"batch: 3 uneven members, {dtype}, default tile, 40 steps against the oracle")
+    cases = _members(dtype)
+    s = torch.cuda.Stream()
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    B.step(20)
+    B.graph_capture(10)
+    B.graph_replay(2)
+    torch.cuda.synchronize()
+    bound = 1e-12 if dtype == "f64" else 2e-6  # measured 1.5e-15 and 1.8e-7
+    for i, c in enumerate(cases):
+        got = gpu_state_as_oracle(B.view(i))
+        d = float(np.max(np.abs(got - oracle_run(c, 40).get_state())))
+        announce(f"batch: member {i} max |dC| {d:.3e}")
+        assert d <= bound, (i, d)
 
 
 def test_autotune_keeps_results(tmp_path):
@@ -126,3 +153,8 @@ def test_full_batch_sweep_equals_sequential():
         D.close()
     announce(f"batch: largest difference from the default tile {worst:.3e}")
     assert worst <= 1e-5
+    # the smallest member against the oracle's own 20-step run of it
+    small = min(range(len(cases)), key=lambda i: cases[i]["solid"].size)
+    d = float(np.max(np.abs(gpu_state_as_oracle(B.view(small)) - oracle_run(cases[small], 20).get_state())))
+    announce(f"batch: member {small} against the oracle, max |dC| {d:.3e}")
+    assert d <= 2e-6, d
