@@ -338,17 +338,27 @@ void ora_step(ora_lattice* L, int64_t nsteps) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Pressure tensor of Sec. 4.1 at the fluid nodes, from the post-stream
+/* Pressure tensor of Sec. 4.1 at every node, from the post-stream
  * populations n of the current state (the distribution at time t that the
- * collision acts on):
+ * collision acts on).  At a fluid node x:
  *   P_ij(x) = sum_a sum_k (c_ki - u_i)(c_kj - u_j) n_k^a(x)
  *           + 1/2 sum_k W_k c_ki c_kj [psi^A(x) G^A(y) psi^B(y) + psi^B(x) G^B(y) psi^A(y)]
- * with y = x + c_k and u = sum_a j^a / sum_a rho^a the velocity of the
- * fluid.  The paper's second term sums over the ordered species pairs with a
+ * with y = x + c_k.  u is the velocity of the fluid, (sum_a j^a + F / 2) /
+ * sum_a rho^a with F = sum_a F^a of Eq. (SCforce): the momentum of the
+ * populations plus half the momentum the force adds in a step.  With it the
+ * normal component of a planar interface at rest is the same on every plane
+ * (mechanical equilibrium); with the populations' momentum alone it is not.
+ * The paper's second term sums over the ordered species pairs with a
  * prefactor 1/4; both orderings give the same bracket, hence 1/2.  Its pair
  * factor (x - x')^2 is read as the dyad (x - x')_i (x - x')_j of a tensor.
  * Wall neighbours enter as in the force (Sec. 2 wall model): their content
- * through psi and the coupling g_wall^a.                                    */
+ * through psi and the coupling g_wall^a.
+ * At a wall node x (the wall taken as a component of the system, as in the
+ * wall slabs of Sec. 4.1) there is no kinetic part and P_ij(x) is the wall's
+ * half of every wall-fluid pair, the same pair term seen from the wall:
+ *   P_ij(x) = 1/2 sum_{k: y fluid} W_k c_ki c_kj
+ *             [g_wall^A psi^A(y) psi(rho_wall^B) + g_wall^B psi^B(y) psi(rho_wall^A)];
+ * wall-wall pairs carry no force and add nothing.                          */
 void ora_pressure_tensor(ora_lattice* L, double* P) {
   forward_fields(L, L->C);
   static const int PI[6] = {0, 1, 2, 0, 0, 1}, PJ[6] = {0, 1, 2, 1, 2, 2};
@@ -359,10 +369,25 @@ void ora_pressure_tensor(ora_lattice* L, double* P) {
         size_t i = node_at(L, x, y, z);
         double* out = P + i * 6;
         for (int c = 0; c < 6; ++c) out[c] = 0.0;
-        if (L->solid[i]) continue;
+        if (L->solid[i]) {
+          for (int c = 0; c < 6; ++c) {
+            double inter = 0.0;
+            for (int k = 1; k < ORA_Q; ++k) {
+              size_t yy = node_at(L, x + CV[k][0], y + CV[k][1], z + CV[k][2]);
+              if (L->solid[yy]) continue;
+              double br = L->p.g_wall[0] * L->psi[yy * 2] * L->psi[i * 2 + 1] +
+                          L->p.g_wall[1] * L->psi[yy * 2 + 1] * L->psi[i * 2];
+              inter += weight_of(L, k) * CV[k][PI[c]] * CV[k][PJ[c]] * br;
+            }
+            out[c] = 0.5 * inter;
+          }
+          continue;
+        }
         double R = L->rho[i * 2] + L->rho[i * 2 + 1];
         double u[3];
-        for (int d = 0; d < 3; ++d) u[d] = (L->j[i * 6 + d] + L->j[i * 6 + 3 + d]) / R;
+        for (int d = 0; d < 3; ++d)
+          u[d] = (L->j[i * 6 + d] + L->j[i * 6 + 3 + d] +
+                  0.5 * (L->F[i * 6 + d] + L->F[i * 6 + 3 + d])) / R;
         for (int c = 0; c < 6; ++c) {
           double kin = 0.0, inter = 0.0;
           for (int k = 0; k < ORA_Q; ++k) {
@@ -381,10 +406,10 @@ void ora_pressure_tensor(ora_lattice* L, double* P) {
 }
 
 /* Eq. (gammaMechDef) on the lattice for interfaces normal to z: the sum over
- * the planes z that hold fluid of the plane mean (over its fluid nodes) of
+ * the planes z of the plane mean (over all its nodes, fluid and wall) of
  * P_N - P_T = P_zz - (P_xx + P_yy) / 2.  A periodic box with two interfaces
  * holds twice the surface tension.  profile (nz values, or NULL): the plane
- * means, 0 for planes without fluid.                                       */
+ * means.                                                                   */
 double ora_surface_tension_z(ora_lattice* L, double* profile) {
   double* P = (double*)malloc(L->N * 6 * sizeof(double));
   ora_pressure_tensor(L, P);
@@ -392,13 +417,9 @@ double ora_surface_tension_z(ora_lattice* L, double* profile) {
   size_t A = (size_t)L->nx * L->ny;
   for (int z = 0; z < L->nz; ++z) {
     double s = 0.0;
-    size_t cnt = 0;
-    for (size_t i = (size_t)z * A; i < (size_t)(z + 1) * A; ++i) {
-      if (L->solid[i]) continue;
+    for (size_t i = (size_t)z * A; i < (size_t)(z + 1) * A; ++i)
       s += P[i * 6 + 2] - 0.5 * (P[i * 6 + 0] + P[i * 6 + 1]);
-      ++cnt;
-    }
-    double m = cnt ? s / (double)cnt : 0.0;
+    double m = s / (double)A;
     if (profile) profile[z] = m;
     total += m;
   }

@@ -113,11 +113,12 @@ void ora_stream(const ora_lattice* L, const double* in, double* out);
 void ora_force(const ora_lattice* L, const double* rho, double* F);
 
 /* Pressure tensor (Sec. 4.1) of the current state at every node:
-   P[node*6 + {xx, yy, zz, xy, xz, yz}], zero at solid nodes. */
+   P[node*6 + {xx, yy, zz, xy, xz, yz}]; at solid nodes the wall's half of
+   the wall-fluid pair terms (no kinetic part). */
 void ora_pressure_tensor(ora_lattice* L, double* P);
 /* Surface tension integral (Eq. gammaMechDef) for interfaces normal to z:
-   sum over planes of the plane mean of P_zz - (P_xx + P_yy)/2 over fluid
-   nodes; profile (nz values) may be NULL. */
+   sum over planes of the plane mean (over all nodes of the plane) of
+   P_zz - (P_xx + P_yy)/2; profile (nz values) may be NULL. */
 double ora_surface_tension_z(ora_lattice* L, double* profile);
 
 /* Eq. (mechRadGamma) about centre[3]: shells of unit width (bin b holds

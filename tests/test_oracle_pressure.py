@@ -6,12 +6,28 @@ tension integral (Eq. gammaMechDef).
   uniform state is g psi_A psi_B (2 W_axis + 8 W_diag) I, because the 18
   neighbours give sum_k W_k c_k c_k = (2 W_axis + 8 W_diag) I.
 * A relaxed planar interface is in mechanical equilibrium: the normal
-  component P_zz is the same on every plane (within 1 %), while the
-  tangential component dips in the interface; far from it P_N - P_T
-  vanishes and P_N equals the bulk pressure (rho_A + rho_B)/3 + 10 g psi psi.
-* Walls: with the same wall content for both species, the A-wall and B-wall
-  systems are mirror images, so their tensions are equal and Young's angle
-  is 90 degrees; a wall richer in A lowers the A-wall tension (A wets).
+  component P_zz is the same on every plane (to 1e-8 relative, with the
+  fluid velocity including half the force; the populations' momentum alone
+  leaves a 0.4 % step), while the tangential component dips in the
+  interface; far from it P_N - P_T vanishes and P_N equals the bulk pressure
+  (rho_A + rho_B)/3 + 10 g psi psi.
+* Scale of the planar tension, without the tensor code: for tau = 1 the
+  stored populations are equilibria, so the plane sum of the kinetic
+  P_xx is sum_z rho(z)/3; P_zz is the bulk pressure on every plane; and the
+  tangential pair term of a plane follows from the psi profile by counting
+  each neighbour class (c_z = 0 or +-1) with its c_x^2.  The oracle's integral
+  equals this closed form.  It is a plane mean (the same for any cross
+  section) summed over all interfaces (two lamellae hold twice the tension of
+  one), and on the lattice it is anisotropic: normal to an axis it lies below
+  the normal to a face diagonal, which lies below the Laplace tension of a
+  free droplet (an average over orientations).
+* Walls, taken as a component: a wall layer carries its half of every
+  wall-fluid pair, 1/2 (W_axis + 2 W_diag) [g_wall^A psi(rho_wall^B) psi^A +
+  g_wall^B psi(rho_wall^A) psi^B] of the first fluid layer for a flat wall,
+  and deeper wall layers nothing.  With the same wall content for both
+  species, the A-wall and B-wall systems are mirror images, so their
+  tensions are equal and Young's angle is 90 degrees; a wall richer in A
+  lowers the A-wall tension (A wets).
 """
 import numpy as np
 import pytest
@@ -62,7 +78,7 @@ def test_planar_interface_mechanical_balance(ora):
     r = L.density()
     pn = P[..., 2].mean(axis=(1, 2))
     pt = 0.5 * (P[..., 0] + P[..., 1]).mean(axis=(1, 2))
-    assert (pn.max() - pn.min()) / pn.mean() < 0.01
+    assert (pn.max() - pn.min()) / pn.mean() < 1e-8
     assert (pt.max() - pt.min()) / pt.mean() > 0.05
     bulk = (r[..., 0] + r[..., 1]) / 3.0 + 10.0 * g * r[..., 0] * r[..., 1]
     for z in (0, 32):  # lamella centres, 16 planes from either interface
@@ -75,6 +91,136 @@ def test_planar_interface_mechanical_balance(ora):
     nz = prof.size
     mirror = prof[(nz // 2 - 1 - np.arange(nz)) % nz]
     assert np.allclose(prof, mirror, atol=1e-9)
+
+
+# the 18 moving D3Q19 velocities, written out here: the six axis vectors and
+# the twelve face diagonals
+_MOVING = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+           (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+           (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+def _closed_form_tension(rho, rho_post, g, wa=1.0, wd=1.0):
+    """Eq. gammaMechDef summed over z for a fluid-only planar system at rest
+    with tau = 1 and psi = rho, from its density profiles alone:
+    sum_z [p_bulk - rho(z)/3 - P_T^pair(z)], where P_T^pair(z) sums
+    1/2 W_k (c_kx^2 + c_ky^2)/2 g [psi_A(z) psi_B(z + c_kz) + psi_B(z) psi_A(z + c_kz)]
+    over the 18 neighbours.  rho: densities of the stored (post-collision)
+    populations, whose second moment the streamed populations carry;
+    rho_post: the post-stream densities, which psi and the bulk pressure
+    at the lamella centre take."""
+    ra = rho_post[..., 0].mean(axis=(1, 2))
+    rb = rho_post[..., 1].mean(axis=(1, 2))
+    rs = rho.sum(axis=-1).mean(axis=(1, 2))
+    nz = ra.size
+    zc = nz // 2
+    p_bulk = (ra[zc] + rb[zc]) / 3.0 + g * (2 * wa + 8 * wd) * ra[zc] * rb[zc]
+    pt = np.zeros(nz)
+    for c in _MOVING:
+        w = wa if sum(abs(v) for v in c) == 1 else wd
+        lat = 0.5 * (c[0] ** 2 + c[1] ** 2)
+        if lat == 0:
+            continue
+        sa, sb = np.roll(ra, -c[2]), np.roll(rb, -c[2])  # psi at z + c_z
+        pt += 0.5 * w * lat * g * (ra * sb + rb * sa)
+    return float(np.sum(p_bulk - rs / 3.0 - pt))
+
+
+def test_planar_tension_closed_form(ora):
+    """The oracle's planar integral equals the closed form from the density
+    profile (scale, plane mean, pair counting), for the unweighted and a
+    weighted stencil."""
+    for g, wa, wd in ((0.1, 1.0, 1.0), (0.0833, 2.0, 1.0)):
+        L = ora.Lattice(W.params(4, 4, 64, g, w_axis=wa, w_diag=wd))
+        z = np.arange(64)[:, None, None] * np.ones((1, 4, 4))
+        inside = (z >= 16) & (z < 48)
+        L.init_equilibrium(np.where(inside, 0.7, 0.04), np.where(inside, 0.04, 0.7))
+        L.step(8000)
+        gamma, _ = L.surface_tension_z()
+        post = L.stream(L.get_state()).sum(axis=-1)
+        closed = _closed_form_tension(L.density(), post, g, wa, wd)
+        # the bulk pressure is the equation of state at the lamella centre,
+        # where the profile is flat to ~1e-7 (measured difference 7e-8)
+        assert abs(gamma - closed) <= 1e-6 * abs(gamma), (g, gamma, closed)
+
+
+def test_planar_tension_per_area_and_per_interface(ora):
+    """A plane mean, not a plane sum: the same tension for a 4 x 4 and a
+    6 x 6 cross section; and a sum over the interfaces: two A lamellae (four
+    interfaces) hold twice the tension of one (two interfaces)."""
+    def run(n, nz, bands):
+        L = ora.Lattice(W.params(n, n, nz, 0.1))
+        z = np.arange(nz)[:, None, None] * np.ones((1, n, n))
+        inside = ((z * bands) % nz >= nz // 4) & ((z * bands) % nz < 3 * nz // 4)
+        L.init_equilibrium(np.where(inside, 0.7, 0.04), np.where(inside, 0.04, 0.7))
+        L.step(6000)
+        return L.surface_tension_z()[0]
+    g4 = run(4, 64, 1)
+    assert abs(run(6, 64, 1) - g4) <= 1e-12 * g4
+    g_two = run(4, 128, 2)
+    assert abs(g_two - 2.0 * g4) <= 1e-6 * g4
+
+
+@pytest.mark.slow
+def test_planar_tension_against_laplace(ora):
+    """Magnitude against the Laplace law at g = 0.1: the slope of dp over
+    1/R of three free droplets gives 2 gamma_L.  The planar tension of one
+    interface normal to an axis lies within 25 % below gamma_L (0.0854
+    against 0.1027 measured), the one normal to a face diagonal between the
+    two (0.0958): the unweighted force stencil makes the interfacial tension
+    anisotropic on the lattice, and a droplet averages over orientations."""
+    n, g, T = 32, 0.1, 3000
+    dps, Rs = [], []
+    for R0 in (6.0, 8.0, 10.0):
+        L = ora.Lattice(W.params(n, n, n, g))
+        ra, rb = W.sphere_densities(n, R0)
+        L.init_equilibrium(ra, rb)
+        L.step(T)
+        r = L.density()
+        p = (r[..., 0] + r[..., 1]) / 3.0 + 10.0 * g * r[..., 0] * r[..., 1]
+        c = n // 2
+        dps.append(p[c - 1:c + 2, c - 1:c + 2, c - 1:c + 2].mean() - p[0:2, 0:2, 0:2].mean())
+        Rs.append((3.0 * np.count_nonzero(r[..., 0] > r[..., 1]) / (4.0 * np.pi)) ** (1.0 / 3.0))
+    gamma_l = np.polyfit(1.0 / np.array(Rs), np.array(dps), 1)[0] / 2.0
+    L = _lamella(ora, g)
+    g100 = L.surface_tension_z()[0] / 2.0
+    # interfaces normal to (1, 1, 0): A where (x + y) mod nb < nb / 2
+    nb = 64
+    L = ora.Lattice(W.params(nb, nb, 2, g))
+    x = np.arange(nb)[None, None, :]
+    y = np.arange(nb)[None, :, None]
+    inside = ((x + y) % nb < nb // 2) * np.ones((2, 1, 1), bool)
+    L.init_equilibrium(np.where(inside, 0.7, 0.04), np.where(inside, 0.04, 0.7))
+    L.step(8000)
+    P = L.pressure_tensor()
+    pn = 0.5 * (P[..., 0] + P[..., 1] + 2.0 * P[..., 3])
+    pt = 0.5 * (0.5 * (P[..., 0] + P[..., 1] - 2.0 * P[..., 3]) + P[..., 2])
+    g110 = float((pn - pt).mean()) * nb / (2.0 * np.sqrt(2.0))  # two interfaces of length nb sqrt 2
+    assert 0.75 * gamma_l < g100 < g110 < gamma_l, (g100, g110, gamma_l)
+
+
+def test_wall_layer_carries_its_half_of_the_pairs(ora):
+    """Wall slab (solid on z < 16, fluid above, periodic): the plane of the
+    top wall layer holds 1/2 (W_axis + 2 W_diag) [g_wall^A psi_wB psi^A +
+    g_wall^B psi_wA psi^B] of the first fluid layer above it, the bottom wall
+    layer the same of the fluid layer below it (through the periodic z
+    boundary), and the wall planes between them nothing."""
+    n, nz, wall, g = 4, 48, 16, 0.1
+    solid = np.zeros((nz, n, n), np.uint8)
+    solid[:wall] = 1
+    rw = (0.3, 0.65)
+    L = ora.Lattice(W.params(n, n, nz, g, rho_wall=rw, g_wall=(0.09, 0.13)), solid)
+    ra = np.where(solid == 1, 0.0, 0.7)
+    rb = np.where(solid == 1, 0.0, 0.04)
+    L.init_equilibrium(ra, rb)
+    L.step(200)
+    _, prof = L.surface_tension_z()
+    post = L.stream(L.get_state()).sum(axis=-1)  # post-stream densities (nz, ny, nx, 2)
+    for zw, zf in ((wall - 1, wall), (0, nz - 1)):
+        pa, pb = post[zf, 0, 0, 0], post[zf, 0, 0, 1]
+        expect = 0.5 * (1.0 + 2.0) * (0.09 * rw[1] * pa + 0.13 * rw[0] * pb)
+        assert abs(prof[zw] - expect) <= 1e-14, (zw, prof[zw], expect)
+    assert np.all(prof[1:wall - 1] == 0.0)
 
 
 def _wall_slab(ora, rho_fluid, rho_wall, g=0.1, n=4, nz=48, wall=16, steps=3000):
