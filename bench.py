@@ -50,49 +50,67 @@ def fluid_nodes(solid):
     return int(np.count_nonzero(np.asarray(solid) == 0))
 
 
-def timed_relaxation(scd, W, torch, dtype, steps, warmup, obs_every, tile, stream):
-    """MLUPS of the relaxation run and the per-launch time of the step kernel."""
+def timed_relaxation(scd, W, torch, dtype, steps, warmup, samples, obs_every, tile, stream):
+    """MLUPS of the relaxation run (median over samples, each exactly `steps`
+    steps after exactly `warmup` untimed ones) and the per-launch time of
+    the step kernel."""
+    import numpy as np
     c = W.config_throughput(delta=0.2, dtype=dtype)
     L = scd.Lattice(c["params"], c["solid"], stream=stream)
     if tile is not None:
         L.set_tile(*tile)
     L.init_equilibrium(c["rho_a"], c["rho_b"])
     nf = fluid_nodes(c["solid"])
-    L.graph_capture(obs_every)
-    reps_w = max(1, warmup // obs_every)
-    reps = max(1, steps // obs_every)
-    for _ in range(reps_w):
-        L.graph_replay(1)
+    L.step(warmup)
     L.observables()
     torch.cuda.synchronize()
-    # timed region: steps with observables every obs_every steps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        L.graph_replay(1)
-        L.observables()
-        L.contact_angle(c["ca"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    nsteps = reps * obs_every
+    # a graph of g steps (even, at most obs_every) serves the blocks; an odd
+    # or short remainder runs eagerly; observables and both contact-angle
+    # estimators after every obs_every-th step and after the last one
+    g = min(obs_every, steps) // 2 * 2
+    walls = []
+    for _ in range(samples):
+        if g >= 2:
+            L.graph_capture(g)  # on the current buffer parity; runs nothing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            if g >= 2 and steps - done >= g:
+                L.graph_replay(1)
+                done += g
+            else:
+                L.step(steps - done)
+                done = steps
+            if done % obs_every == 0 or done == steps:
+                L.observables()
+                L.contact_angle(c["ca"])
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    wall = float(np.median(walls))
     # kernel-only region on the kernel's stream: average launch duration
+    gk = max(2, g)
+    L.graph_capture(gk)
+    reps = max(1, steps // gk)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     L.graph_replay(reps)
     e1.record(stream)
     torch.cuda.synchronize()
-    launch_ms = e0.elapsed_time(e1) / nsteps
+    launch_ms = e0.elapsed_time(e1) / (reps * gk)
     # layout ceiling: the step's pulls and stores without its arithmetic
     e0.record(stream)
-    for _ in range(nsteps):
+    for _ in range(reps * gk):
         L.pull_copy()
     e1.record(stream)
     torch.cuda.synchronize()
-    copy_ms = e0.elapsed_time(e1) / nsteps
+    copy_ms = e0.elapsed_time(e1) / (reps * gk)
     ca = L.contact_angle(c["ca"])
     variant, zc = L.tile()
     tx, ty, zmarch, waves = scd.tile_list()[variant]
-    return {"mlups": nf * nsteps / wall / 1e6, "ms_per_step": wall * 1e3 / nsteps, "steps": nsteps,
+    return {"mlups": nf * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps, "steps": steps,
+            "samples_mlups": [round(nf * steps / w / 1e6, 1) for w in walls],
             "launch_ms": launch_ms, "pull_copy_ms": copy_ms, "fluid_nodes": nf,
             "theta_e1": ca["theta_e1"],
             "theta_e2": ca["theta_e2"],
@@ -133,24 +151,43 @@ def autotuned_tile(scd, W, dtype, stream):
 
 
 def fp32_vs_fp64(scd, W, torch, steps, tile64, tile32, stream):
+    """The throughput run for `steps` steps in FP64, in FP32, and in FP64 with
+    the state rounded to FP32 after every step (FP64 arithmetic, FP32
+    storage): the last shows how far rounding at the FP32 level alone moves
+    the densities over the run, next to the FP32 run's difference."""
     import numpy as np
     out = {}
     dens = {}
-    for dt, tile in (("f64", tile64), ("f32", tile32)):
+    mass = {}
+    for name, dt, tile in (("f64", "f64", tile64), ("f32", "f32", tile32), ("f64_f32_storage", "f64", tile64)):
         c = W.config_throughput(delta=0.2, dtype=dt)
         L = scd.Lattice(c["params"], c["solid"], stream=stream)
         if tile is not None:
             L.set_tile(*tile)
         L.init_equilibrium(c["rho_a"], c["rho_b"])
-        L.step(steps)
-        out[dt] = L.contact_angle(c["ca"])
-        dens[dt] = L.density().cpu().numpy()
+        m0 = L.observables()["mass"]
+        if name == "f64_f32_storage":
+            buf = L.empty_blocked()
+            for t in range(1, steps + 1):
+                L.step(1)
+                st = L.get_state(out=buf, blocked=True)
+                st.copy_(st.float().double())
+                L.set_state(st, step=t, blocked=True)
+        else:
+            L.step(steps)
+        m1 = L.observables()["mass"]
+        mass[name] = [(m1[a] - m0[a]) / m0[a] for a in range(2)]
+        out[name] = L.contact_angle(c["ca"])
+        dens[name] = L.density().cpu().numpy()
+        L.close()
     return {"steps": steps,
             "max_abs_drho": float(np.max(np.abs(dens["f64"] - dens["f32"]))),
+            "max_abs_drho_f64_f32_storage": float(np.max(np.abs(dens["f64"] - dens["f64_f32_storage"]))),
             "theta_e1_f64": out["f64"]["theta_e1"], "theta_e1_f32": out["f32"]["theta_e1"],
             "theta_e2_f64": out["f64"]["theta_e2"], "theta_e2_f32": out["f32"]["theta_e2"],
             "dtheta_e1": abs(out["f64"]["theta_e1"] - out["f32"]["theta_e1"]),
-            "dtheta_e2": abs(out["f64"]["theta_e2"] - out["f32"]["theta_e2"])}
+            "dtheta_e2": abs(out["f64"]["theta_e2"] - out["f32"]["theta_e2"]),
+            "mass_drift_rel": mass}
 
 
 def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
@@ -201,7 +238,7 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
     gs.forward()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    gs.backward()
+    grad = gs.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return {"workload": "64x64x48 droplet r=14, " + dtype, "forward_ms": round(fwd, 4),
@@ -209,14 +246,29 @@ def adjoint_cost(scd, W, torch, stream, dtype="f64", nsteps=40):
             "adjoint_ms": round(adj, 4), "ratio": round(adj / fwd, 3),
             "grad_finite": all(x == x for x in g),
             "checkpointed_2000_steps": {"forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
-                                        "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}}
+                                        "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+                                        "theta_e2": gs.theta, "grad": grad}}
 
 
-def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):
-    """The 64-droplet FP32 sweep: one batched launch per step (tiles picked by
-    the batch autotuner, hipGraph replay) against the same droplets stepped
-    one launch each, with the library's default tiles and with each
-    lattice's autotuned tile; the speedup is taken against the faster."""
+def _angles(lat, cfg):
+    """(theta_E1, theta_E2), or None when no droplet is left (members below
+    the coexistence coupling dissolve)."""
+    ca = lat.contact_angle(cfg)
+    if ca.get("status", 0) != 0 or ca["theta_e1"] != ca["theta_e1"] or ca["theta_e2"] != ca["theta_e2"]:
+        return None
+    return (ca["theta_e1"], ca["theta_e2"])
+
+
+def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, seq_default_steps=200,
+                          n=64):
+    """The batched parameter sweep: 64 FP32 droplets drawn from seed 0, run
+    for `steps` steps in one batched launch per step (tiles picked by the
+    batch autotuner, a captured graph of graph_steps steps replayed), against
+    the same 64 droplets run one after another, one launch per step each,
+    with each lattice's autotuned tile for the same number of steps (and,
+    for the rate only, with the library's default tile over
+    seq_default_steps).  Both sides start from the same seeded state; the
+    contact angles of every droplet at the end are compared."""
     draws = W.batch_draw(n, seed=0)
     cases = [W.droplet_case(d["nx"], d["ny"], d["nz"], d["radius"], d["g_ab"], d["delta"], dtype="f32")
              for d in draws]
@@ -227,44 +279,59 @@ def batched_vs_sequential(scd, W, torch, stream, steps=40, n=64):
     tile, _ = B.autotune(3, None)
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
-    B.graph_capture(20)
-    B.graph_replay(1)
+    B.graph_capture(graph_steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    B.graph_replay(steps // 20)
+    B.graph_replay(steps // graph_steps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    th_b = [_angles(B.view(i), c["ca"]) for i, c in enumerate(cases)]
     del B
     torch.cuda.empty_cache()
-    lats = []
-    for c in cases:
-        L = scd.Lattice(c["params"], c["solid"], stream=stream)
-        L.init_equilibrium(c["rho_a"], c["rho_b"])
-        lats.append(L)
 
-    def sequential():
-        for L in lats:
-            L.step(2)
+    def timed_runs(lats, nsteps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            for L in lats:
-                L.step(1)
+        for L in lats:
+            L.step(nsteps)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    ts_default = sequential()
-    for L in lats:
-        L.autotune(3, None)
-    ts_tuned = sequential()
-    ts = min(ts_default, ts_tuned)
+    def fresh(tuned):
+        lats = []
+        for c in cases:
+            L = scd.Lattice(c["params"], c["solid"], stream=stream)
+            L.init_equilibrium(c["rho_a"], c["rho_b"])
+            if tuned:
+                L.autotune(3, None)
+                L.init_equilibrium(c["rho_a"], c["rho_b"])
+            lats.append(L)
+        return lats
+
+    lats = fresh(False)
+    timed_runs(lats, 2)  # warm-up
+    ts_default = timed_runs(lats, seq_default_steps) / seq_default_steps
+    lats = fresh(True)
+    ts_tuned = timed_runs(lats, steps) / steps
+    th_s = [_angles(L, c["ca"]) for L, c in zip(lats, cases)]
+    del lats
+    torch.cuda.empty_cache()
+    both = [(a, b) for a, b in zip(th_b, th_s) if a is not None and b is not None]
     tl = scd.tile_list()
+    per_step_b = tb / steps
     return {"droplets": n, "fluid_nodes": nf, "dtype": "f32", "steps": steps,
-            "batched_mlups": round(nf * steps / tb / 1e6, 1),
+            "graph_steps": graph_steps,
+            "batched_mlups": round(nf / per_step_b / 1e6, 1),
             "batched_tile": {"shape": list(tl[tile[0]]), "zchunk": tile[1], "grid": tile[2]},
-            "sequential_default_mlups": round(nf * steps / ts_default / 1e6, 1),
-            "sequential_tuned_mlups": round(nf * steps / ts_tuned / 1e6, 1),
-            "speedup": round(ts / tb, 3)}
+            "sequential_tuned_mlups": round(nf / ts_tuned / 1e6, 1),
+            "sequential_default_mlups": round(nf / ts_default / 1e6, 1),
+            "sequential_default_steps": seq_default_steps,
+            "speedup": round(min(ts_default, ts_tuned) / per_step_b, 3),
+            "theta": {"droplets_compared": len(both),
+                      "no_droplet_both": sum(1 for a, b in zip(th_b, th_s) if a is None and b is None),
+                      "no_droplet_one_side": sum(1 for a, b in zip(th_b, th_s) if (a is None) != (b is None)),
+                      "max_dtheta_e1": max((abs(a[0] - b[0]) for a, b in both), default=None),
+                      "max_dtheta_e2": max((abs(a[1] - b[1]) for a, b in both), default=None)}}
 
 
 def copy_probe(torch, scd, stream, nbytes=1 << 30, reps=20):
@@ -318,11 +385,21 @@ def cpu_baseline(W, seconds):
                 return steps, el
 
     cores = oracle.num_threads()
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     steps, el = sample(seconds)
     oracle.set_threads(1)
     steps1, el1 = sample(seconds / 3)
     oracle.set_threads(cores)
     return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"128x128x64 droplet, FP64, {steps} steps ({el:.1f} s)",
             "one_core": {"value": round(nf * steps1 / el1 / 1e6, 3),
                          "sample": f"{steps1} steps ({el1:.1f} s), 1 thread"}}
@@ -333,6 +410,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--samples", type=int, default=3,
+                    help="timed samples of --steps steps each; the median is reported")
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--theta-steps", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -350,8 +429,10 @@ def main():
         print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(one process drives one GPU)", file=sys.stderr)
         sys.exit(2)
-    if args.obs_every % 2:
-        args.obs_every += 1
+    if args.steps < 1 or args.warmup < 0 or args.samples < 1 or args.obs_every < 1:
+        print("bench.py: need --steps >= 1, --warmup >= 0, --samples >= 1, --obs-every >= 1",
+              file=sys.stderr)
+        sys.exit(2)
 
     import torch
     import paper_0910_3915_amd as scd
@@ -370,12 +451,13 @@ def main():
 
     dt = args.dtype
     log("timing %s relaxation run" % dt.upper())
-    r64 = timed_relaxation(scd, W, torch, dt, args.steps, args.warmup, args.obs_every,
+    r64 = timed_relaxation(scd, W, torch, dt, args.steps, args.warmup, args.samples, args.obs_every,
                            tile64 if dt == "f64" else tile32, stream)
     log(json.dumps(r64))
     result = {
         "metric": METRIC, "value": round(r64["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": r64["steps"], "warmup": args.warmup, "ms_per_step": round(r64["ms_per_step"], 5),
+        "steps": r64["steps"], "warmup": args.warmup, "samples": args.samples,
+        "samples_mlups": r64["samples_mlups"], "ms_per_step": round(r64["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic (seeded droplet, no dataset)",
         "config": {"workload": "single droplet 128x128x64, cap r=24, g_ab=g_wall=0.12, tau=1, "
@@ -386,15 +468,24 @@ def main():
     }
     if not args.no_extras:
         log("timing FP32 relaxation run")
-        r32 = timed_relaxation(scd, W, torch, "f32", args.steps, args.warmup, args.obs_every, tile32, stream)
+        r32 = timed_relaxation(scd, W, torch, "f32", args.steps, args.warmup, args.samples,
+                               args.obs_every, tile32, stream)
         result["fp32"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
                           "ms_per_step": round(r32["ms_per_step"], 5), "tile": r32["tile"],
                           "roofline": roofline(r32, 304, measured_traffic("f32"))}
         log("FP32 vs FP64 after %d steps" % args.theta_steps)
         result["fp32_vs_fp64"] = fp32_vs_fp64(scd, W, torch, args.theta_steps, tile64, tile32, stream)
         log("adjoint / forward cost")
-        result["adjoint"] = {"f64": adjoint_cost(scd, W, torch, stream, "f64"),
-                             "f32": adjoint_cost(scd, W, torch, stream, "f32")}
+        adj = {"f64": adjoint_cost(scd, W, torch, stream, "f64"),
+               "f32": adjoint_cost(scd, W, torch, stream, "f32")}
+        g64 = adj["f64"]["checkpointed_2000_steps"]["grad"]
+        g32 = adj["f32"]["checkpointed_2000_steps"]["grad"]
+        gmax = max(abs(v) for v in g64)
+        # the FP32 gradient of (theta_E2 - 120)^2 over the 2000-step run
+        # against the FP64 one, per component relative to the largest
+        adj["f32_vs_f64_grad"] = {"max_rel_to_largest": max(abs(a - b) for a, b in zip(g32, g64)) / gmax,
+                                  "per_component_rel": [abs(a - b) / abs(b) for a, b in zip(g32, g64)]}
+        result["adjoint"] = adj
         log("batched vs sequential")
         result["batched"] = batched_vs_sequential(scd, W, torch, stream)
     result["copy_probe"] = copy_probe(torch, scd, stream)

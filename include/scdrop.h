@@ -175,23 +175,27 @@ scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step);
 scd_status scd_density(scd_lattice* h, double* d_rho);
 
 /* Pressure tensor of Sec. 4.1 at every node, from the post-stream
- * populations of the current state:
+ * populations of the current state.  At a fluid node
  *   P_ij = sum_a sum_k (c_ki - u_i)(c_kj - u_j) n_k^a
  *        + 1/2 sum_k W_k c_ki c_kj [psi^A G^A(y) psi^B(y) + psi^B G^B(y) psi^A(y)],
- * y = x + c_k, u = sum_a j^a / sum_a rho^a, G = g_ab at fluid and g_wall^a
- * at wall neighbours (whose psi is that of the wall content).  The paper's
- * 1/4 over the two ordered species pairs gives 1/2; its pair factor is the
- * dyad of x - x'.  d_P: caller-owned 6 * N doubles, component-major
- * d_P[c * N + i] with c = xx, yy, zz, xy, xz, yz; zero at wall nodes.
+ * y = x + c_k, u = (sum_a j^a + F / 2) / sum_a rho^a the velocity of the
+ * fluid (F the node's total Shan-Chen and wall force), G = g_ab at fluid and
+ * g_wall^a at wall neighbours (whose psi is that of the wall content).  The
+ * paper's 1/4 over the two ordered species pairs gives 1/2; its pair factor
+ * is the dyad of x - x'.  At a wall node (the wall as a component of the
+ * system) there is no kinetic part; the tensor is the wall's half of each
+ * wall-fluid pair, 1/2 sum_{k: y fluid} W_k c_ki c_kj [g_wall^A psi^A(y)
+ * psi_w^B + g_wall^B psi^B(y) psi_w^A].  d_P: caller-owned 6 * N doubles,
+ * component-major d_P[c * N + i] with c = xx, yy, zz, xy, xz, yz.
  * Asynchronous on the handle's stream. */
 scd_status scd_pressure_tensor(scd_lattice* h, double* d_P);
 
 /* Surface tension integral of Eq. (gammaMechDef) for interfaces normal to z:
- * *h_gamma = sum over the planes z of the mean, over the plane's fluid nodes,
- * of P_N - P_T = P_zz - (P_xx + P_yy) / 2 (planes without fluid add 0).  A
- * periodic box with two interfaces holds twice the tension.  d_P: scratch of
- * 6 * N doubles (left holding the pressure tensor); h_profile: nz host
- * doubles for the plane means, or NULL.  Synchronises. */
+ * *h_gamma = sum over the planes z of the mean, over all nodes of the plane
+ * (fluid and wall), of P_N - P_T = P_zz - (P_xx + P_yy) / 2.  A periodic box
+ * with two interfaces holds twice the tension.  d_P: scratch of 6 * N
+ * doubles (left holding the pressure tensor); h_profile: nz host doubles for
+ * the plane means, or NULL.  Synchronises. */
 scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
                                  double* h_profile);
 

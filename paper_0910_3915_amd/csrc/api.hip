@@ -420,7 +420,7 @@ scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
   scd_status st = scd_pressure_tensor(h, d_P);
   if (st) return st;
   double* planes = (double*)h->wd(h->wl.planes);
-  HIPCHK(launch_plane_tension(h->links(), h->p.nx, h->p.ny, h->p.nz, d_P, planes, h->stream));
+  HIPCHK(launch_plane_tension(h->p.nx, h->p.ny, h->p.nz, d_P, planes, h->stream));
   std::vector<double> prof(h->p.nz);
   HIPCHK(hipMemcpyAsync(prof.data(), planes, prof.size() * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

@@ -78,8 +78,8 @@ hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, in
 hipError_t launch_radial(int dtype, const void* pop, const uint32_t* links, int nx, int ny, int nz,
                          const double* c, int periodic, int nbins, double* P, double* shells,
                          hipStream_t s);
-hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
-                                double* profile, hipStream_t s);
+hipError_t launch_plane_tension(int nx, int ny, int nz, const double* P, double* profile,
+                                hipStream_t s);
 hipError_t launch_stream_copy(const double* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_pull_copy(int dtype, const void* src, const uint32_t* links, void* dst, int nx,
                             int ny, int nz, hipStream_t s);

@@ -503,13 +503,18 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
 // ----------------------------------------------------------------------------
 // Pressure tensor (Sec. 4.1) at every node from the post-stream populations
 // of the current state; rho: their densities at every node (2 N values).
+// At a fluid node
 //   P_ij = sum_a sum_k (c_ki - u_i)(c_kj - u_j) n_k^a
 //        + 1/2 sum_k W_k c_ki c_kj [psi^A G^A(y) psi^B(y) + psi^B G^B(y) psi^A(y)]
-// with y = x + c_k and u = sum_a j^a / sum_a rho^a; the paper's sum over the
-// two ordered species pairs with prefactor 1/4 gives the 1/2, its pair factor
-// is the dyad of (x - x'), and wall neighbours carry their content and
-// g_wall^a as in the force.  Output P[c * N + i] (FP64), c = xx, yy, zz, xy,
-// xz, yz; zero at wall nodes.
+// with y = x + c_k and u the velocity of the fluid, (sum_a j^a + F / 2) /
+// sum_a rho^a (F the total Shan-Chen and wall force of the node, from the
+// same neighbour sums); the paper's sum over the two ordered species pairs
+// with prefactor 1/4 gives the 1/2, its pair factor is the dyad of (x - x'),
+// and wall neighbours carry their content and g_wall^a as in the force.  At a
+// wall node (the wall taken as a component) there is no kinetic part and the
+// tensor is the wall's half of each wall-fluid pair,
+//   1/2 sum_{k: y fluid} W_k c_ki c_kj [g_wall^A psi^A(y) psi_w^B + g_wall^B psi^B(y) psi_w^A].
+// Output P[c * N + i] (FP64), c = xx, yy, zz, xy, xz, yz.
 template <typename real>
 __global__ __launch_bounds__(256) void k_pressure(const real* __restrict__ pop,
                                                   const uint32_t* __restrict__ links,
@@ -519,31 +524,31 @@ __global__ __launch_bounds__(256) void k_pressure(const real* __restrict__ pop,
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const uint32_t lb = links[i];
     double out[6] = {0, 0, 0, 0, 0, 0};
-    if (!(lb & SELF_SOLID)) {
-      int xs[3], ys[3], zs[3];
-      axis3(i % nx, nx, xs);
-      axis3((i / nx) % ny, ny, ys);
-      axis3(i / (nx * ny), nz, zs);
+    int xs[3], ys[3], zs[3];
+    axis3(i % nx, nx, xs);
+    axis3((i / nx) % ny, ny, ys);
+    axis3(i / (nx * ny), nz, zs);
+    if (lb & SELF_SOLID) {
+      const double wA = (double)ph.gw[0] * (double)ph.psiw[1];  // felt by A from this wall node
+      const double wB = (double)ph.gw[1] * (double)ph.psiw[0];
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        if ((lb >> k) & 1u) continue;  // wall-wall pairs carry no force
+        const int y = nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
+        const double qA = psi_of(ph.psi_form, (double)rho[y]);
+        const double qB = psi_of(ph.psi_form, (double)rho[(size_t)N + y]);
+        const double w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const double br = 0.5 * w * (wA * qA + wB * qB);
+        out[0] += CX[k] * CX[k] * br; out[1] += CY[k] * CY[k] * br; out[2] += CZ[k] * CZ[k] * br;
+        out[3] += CX[k] * CY[k] * br; out[4] += CX[k] * CZ[k] * br; out[5] += CY[k] * CZ[k] * br;
+      }
+    } else {
       real n[38];
       pull38(pop, pop_geo(nx, ny, nz), xs, ys, zs, nx, lb, n);
-      double R = 0, j[3] = {0, 0, 0}, m[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const double f = (double)n[k] + (double)n[Q + k];
-        R += f;
-        j[0] += CX[k] * f; j[1] += CY[k] * f; j[2] += CZ[k] * f;
-        m[0] += CX[k] * CX[k] * f; m[1] += CY[k] * CY[k] * f; m[2] += CZ[k] * CZ[k] * f;
-        m[3] += CX[k] * CY[k] * f; m[4] += CX[k] * CZ[k] * f; m[5] += CY[k] * CZ[k] * f;
-      }
-      const double u[3] = {j[0] / R, j[1] / R, j[2] / R};
-      // sum_k (c - u)_i (c - u)_j f = M_ij - u_i J_j - J_i u_j + R u_i u_j
-      const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        out[c] = m[c] - u[ci[c]] * j[cj[c]] - j[ci[c]] * u[cj[c]] + R * u[ci[c]] * u[cj[c]];
       const double pA = psi_of(ph.psi_form, (double)rho[i]);
       const double pB = psi_of(ph.psi_form, (double)rho[(size_t)N + i]);
-      double t[6] = {0, 0, 0, 0, 0, 0};
+      // pair terms and the force sums S^a = sum_k W_k G^a psi^b(y) c_k
+      double t[6] = {0, 0, 0, 0, 0, 0}, sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         const bool wall = (lb >> k) & 1u;
@@ -558,20 +563,39 @@ __global__ __launch_bounds__(256) void k_pressure(const real* __restrict__ pop,
         const double br = w * (pA * gA * qB + pB * gB * qA);
         t[0] += CX[k] * CX[k] * br; t[1] += CY[k] * CY[k] * br; t[2] += CZ[k] * CZ[k] * br;
         t[3] += CX[k] * CY[k] * br; t[4] += CX[k] * CZ[k] * br; t[5] += CY[k] * CZ[k] * br;
+        const double eA = w * gA * qB, eB = w * gB * qA;
+        sA[0] += CX[k] * eA; sA[1] += CY[k] * eA; sA[2] += CZ[k] * eA;
+        sB[0] += CX[k] * eB; sB[1] += CY[k] * eB; sB[2] += CZ[k] * eB;
       }
+      double R = 0, j[3] = {0, 0, 0}, m[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int c = 0; c < 6; ++c) out[c] += 0.5 * t[c];
+      for (int k = 0; k < Q; ++k) {
+        const double f = (double)n[k] + (double)n[Q + k];
+        R += f;
+        j[0] += CX[k] * f; j[1] += CY[k] * f; j[2] += CZ[k] * f;
+        m[0] += CX[k] * CX[k] * f; m[1] += CY[k] * CY[k] * f; m[2] += CZ[k] * CZ[k] * f;
+        m[3] += CX[k] * CY[k] * f; m[4] += CX[k] * CZ[k] * f; m[5] += CY[k] * CZ[k] * f;
+      }
+      // F = F^A + F^B = -psi^A S^A - psi^B S^B; u = (J + F / 2) / R
+      double u[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * (-pA * sA[d] - pB * sB[d])) / R;
+      // sum_k (c - u)_i (c - u)_j f = M_ij - u_i J_j - J_i u_j + R u_i u_j
+      const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        out[c] = m[c] - u[ci[c]] * j[cj[c]] - j[ci[c]] * u[cj[c]] + R * u[ci[c]] * u[cj[c]] +
+                 0.5 * t[c];
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) P[(size_t)c * N + i] = out[c];
   }
 }
 
-// One workgroup per plane z: mean over its fluid nodes of P_zz - (P_xx +
-// P_yy) / 2 (Eq. gammaMechDef's integrand for interfaces normal to z), 0 for
-// a plane without fluid.
-__global__ __launch_bounds__(256) void k_plane_tension(const uint32_t* __restrict__ links, int nx,
-                                                       int ny, int nz,
+// One workgroup per plane z: mean over all its nodes (fluid and wall) of
+// P_zz - (P_xx + P_yy) / 2, Eq. gammaMechDef's integrand for interfaces
+// normal to z.
+__global__ __launch_bounds__(256) void k_plane_tension(int nx, int ny, int nz,
                                                        const double* __restrict__ P,
                                                        double* __restrict__ profile) {
   __shared__ double sh[2 * 16];
@@ -580,12 +604,11 @@ __global__ __launch_bounds__(256) void k_plane_tension(const uint32_t* __restric
   double v[2] = {0, 0};
   for (int t = threadIdx.x; t < A; t += blockDim.x) {
     const int i = z * A + t;
-    if (links[i] & SELF_SOLID) continue;
     v[0] += P[(size_t)2 * N + i] - 0.5 * (P[i] + P[(size_t)N + i]);
     v[1] += 1.0;
   }
   block_sum<2>(v, sh);
-  if (threadIdx.x == 0) profile[z] = v[1] > 0 ? v[0] / v[1] : 0.0;
+  if (threadIdx.x == 0) profile[z] = v[0] / v[1];
 }
 
 // Radial decomposition about a centre c (Eq. mechRadGamma): per fluid node,
@@ -694,9 +717,9 @@ hipError_t launch_pressure(int dtype, const void* pop, const uint32_t* links, in
   return hipGetLastError();
 }
 
-hipError_t launch_plane_tension(const uint32_t* links, int nx, int ny, int nz, const double* P,
-                                double* profile, hipStream_t s) {
-  hipLaunchKernelGGL(k_plane_tension, dim3(nz), dim3(256), 0, s, links, nx, ny, nz, P, profile);
+hipError_t launch_plane_tension(int nx, int ny, int nz, const double* P, double* profile,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_plane_tension, dim3(nz), dim3(256), 0, s, nx, ny, nz, P, profile);
   return hipGetLastError();
 }
 
