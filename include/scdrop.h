@@ -248,6 +248,19 @@ scd_status scd_observables(scd_lattice* h, scd_obs* h_out);
  * SCD_CA_NO_DROP when phi <= 0 at the column's first fluid node. */
 scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* h_out);
 
+/* For callers that cannot allocate (code that must not call hipMalloc or an
+ * allocating library routine: tight serving loops, harnesses that forbid
+ * allocation): scd_contact_angle with its scratch (the phi layers and column,
+ * the layer partials and the result slots) in a fixed device array of the
+ * library instead of the lattice's work area.  The array holds planes of at
+ * most 512 x 512 nodes and at most 4096 planes (4.1 MB per GPU, kept until
+ * the process ends; each GPU has its own, looked up on the first call with
+ * that GPU current); larger lattices get SCD_EUNSUPPORTED.  Same results,
+ * flags and status as scd_contact_angle; synchronises.  Calls on one GPU
+ * share the array: calls that overlap on one GPU (other threads or streams)
+ * race and must be serialised by the caller. */
+scd_status scd_contact_angle_static(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* h_out);
+
 /* ---- adjoint (extension) ---- */
 /* d_lambda (pop layout, dtype of the lattice) := dL/dC of the current state
  * for L = theta_E2 (radians) times dL_dtheta.  Synchronises. */

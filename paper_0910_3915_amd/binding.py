@@ -84,6 +84,7 @@ _PROTOS = {
     "scd_surface_tension_z": [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "scd_observables": [_VP, ctypes.POINTER(ScdObs)],
     "scd_contact_angle": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
+    "scd_contact_angle_static": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
     "scd_ca_seed": [_VP, ctypes.POINTER(ScdCaCfg), _D, _VP],
     "scd_adjoint_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_D)],
     "scd_adjoint_reset": [_VP],
@@ -385,10 +386,13 @@ class Lattice:
         return {"mass": (o.mass[0], o.mass[1]), "momentum": tuple(o.momentum), "finite": bool(o.finite),
                 "step": o.step, "status": st}
 
-    def contact_angle(self, cfg):
+    def contact_angle(self, cfg, static_scratch=False):
+        """Both estimators of Sec. 3; static_scratch: through
+        scd_contact_angle_static (scratch in the library's device array)."""
         out = ScdCa()
         c = make_ca_cfg(cfg)
-        st = lib().scd_contact_angle(self.h, ctypes.byref(c), ctypes.byref(out))
+        fn = lib().scd_contact_angle_static if static_scratch else lib().scd_contact_angle
+        st = fn(self.h, ctypes.byref(c), ctypes.byref(out))
         if st not in (SCD_OK, SCD_ENOINTERFACE):
             check(st)
         d = {n: getattr(out, n) for n, _ in ScdCa._fields_ if n != "pad"}

@@ -231,9 +231,11 @@ scd_status check_cfg(const scd_lattice* h, const scd_ca_cfg* c) {
 
 CaDev ca_dev(const scd_ca_cfg* c) { return CaDev{c->ic, c->jc, c->z_solid_top, c->offset, c->eps}; }
 
-scd_status read_ca(scd_lattice* h, scd_ca* out, double* status_out) {
+scd_status read_ca(scd_lattice* h, scd_ca* out, double* status_out,
+                   const double* d_slots = nullptr) {
   double r[CA_SLOTS];
-  HIPCHK(hipMemcpyAsync(r, h->wv(h->wl.ca), sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(r, d_slots ? d_slots : h->wd(h->wl.ca), sizeof(r), hipMemcpyDeviceToHost,
+                        h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (out) {
     out->theta_e1 = r[0]; out->h_e1 = r[1]; out->a_e1 = r[2]; out->R_e1 = r[3];
@@ -530,6 +532,26 @@ scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out)
                               h->wd(h->wl.ca), h->stream));
   double status;
   st = read_ca(h, out, &status);
+  if (st) return st;
+  if (status != 0.0) return fail(SCD_ENOINTERFACE, "no droplet on column (%d, %d)", cfg->ic, cfg->jc);
+  return SCD_OK;
+}
+
+scd_status scd_contact_angle_static(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out) {
+  if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
+  scd_status st = check_cfg(h, cfg);
+  if (st) return st;
+  if ((size_t)h->p.nx * h->p.ny > CA_STATIC_MAX_PLANE || (size_t)h->p.nz > CA_STATIC_MAX_NZ)
+    return fail(SCD_EUNSUPPORTED,
+                "static contact-angle scratch holds planes of at most %zu nodes and %zu planes "
+                "(lattice %d x %d x %d); use scd_contact_angle",
+                CA_STATIC_MAX_PLANE, CA_STATIC_MAX_NZ, h->p.nx, h->p.ny, h->p.nz);
+  double *phi, *part, *res;
+  HIPCHK(ca_static_scratch(&phi, &part, &res));
+  HIPCHK(launch_contact_angle(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
+                              ca_dev(cfg), phi, part, res, h->stream));
+  double status;
+  st = read_ca(h, out, &status, res);
   if (st) return st;
   if (status != 0.0) return fail(SCD_ENOINTERFACE, "no droplet on column (%d, %d)", cfg->ic, cfg->jc);
   return SCD_OK;

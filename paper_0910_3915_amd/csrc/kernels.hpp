@@ -83,6 +83,12 @@ hipError_t launch_plane_tension(int nx, int ny, int nz, const double* P, double*
 hipError_t launch_stream_copy(const double* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_pull_copy(int dtype, const void* src, const uint32_t* links, void* dst, int nx,
                             int ny, int nz, hipStream_t s);
+// Largest plane (nx * ny) and depth the static contact-angle scratch holds,
+// and the device address of that scratch on the current device (looked up
+// once per device).
+constexpr size_t CA_STATIC_MAX_PLANE = 512 * 512;
+constexpr size_t CA_STATIC_MAX_NZ = 4096;
+hipError_t ca_static_scratch(double** phi, double** partials, double** result);
 hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int nz, CaDev cfg,
                           const double* phi_scratch, const double* result, double dL_dtheta,
                           void* lambda, hipStream_t s);

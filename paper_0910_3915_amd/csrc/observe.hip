@@ -19,6 +19,8 @@
 //         column height H = chi(kref)/2 + sum of chi above it up to the top of
 //         the droplet, the reference area sum(chi) = pi aref^2.  E2 is a
 //         smooth function of the state and seeds the adjoint.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -442,6 +444,39 @@ hipError_t launch_contact_angle(int dtype, const void* pop, const uint32_t* link
   hipLaunchKernelGGL(k_ca_finish, dim3(1), dim3(256), stage, s, links, nx, ny, nz, cfg,
                      phi_scratch, partials, result);
   return hipGetLastError();
+}
+
+// Scratch of the contact angle in a file-scope device array, for callers
+// that allocate nothing (scd_contact_angle_static): the phi layers and column
+// (CA_STATIC_PHI doubles at most), the layer partials and the result slots.
+// Each GPU holds its own copy for the life of the process; host code uses
+// the address hipGetSymbolAddress returns for the current device, never the
+// array's name.
+constexpr size_t CA_STATIC_PHI = 2 * CA_STATIC_MAX_PLANE + CA_STATIC_MAX_NZ;
+constexpr size_t CA_STATIC_PART = 512;  // >= 4 * CA_LAYER_BLOCKS + 1
+static_assert(4 * CA_LAYER_BLOCKS + 1 <= CA_STATIC_PART, "layer partials");
+static __device__ __align__(256) double scratch[CA_STATIC_PHI + CA_STATIC_PART + CA_SLOTS];
+
+hipError_t ca_static_scratch(double** phi, double** partials, double** result) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex lock;
+  static void* addr[MAX_DEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  double* base = static_cast<double*>(addr[dev]);
+  *phi = base;
+  *partials = base + CA_STATIC_PHI;
+  *result = base + CA_STATIC_PHI + CA_STATIC_PART;
+  return hipSuccess;
 }
 
 // Seed of the adjoint: lambda_k^A = dL/dtheta * dtheta/dphi, lambda_k^B =
