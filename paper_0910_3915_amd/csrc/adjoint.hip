@@ -9,10 +9,12 @@
 //      force from the neighbours' post-stream densities, velocities) and
 //      transpose the collision (Eq. Equil), the velocity shift and the local
 //      part of the force; store q^a = psi^a dL/dF^a, D^a = dL/drho^a and
-//      E^a = dL/dj^a, and accumulate the parameter gradient;
+//      E^a = dL/dj^a, and accumulate the gradient of the wall parameters;
 //   2. per node: add the transposed force stencil, i.e. the gather
 //      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) to D (FP32: as
-//      a pass of its own), then stream transposed with bounce-back, as a push of
+//      a pass of its own), with the same gather giving the g_ab gradient
+//      (-psi^b(y) times it, summed), then stream transposed with
+//      bounce-back, as a push of
 //      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k to x - c_k (or to the
 //      node itself on the opposite velocity next to a wall).
 #include "common.hpp"
@@ -106,6 +108,13 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
   const PopGeo pg = pop_geo(nx, ny, nz);
   const int stride = gridDim.x * blockDim.x;
   double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
+  // neighbour densities and lambda' are read at a uniform base plus a 32-bit
+  // byte offset (a field of N reals and a species of lambda stay below 4 GiB)
+  constexpr uint32_t SZ = sizeof(real);
+  const char* __restrict__ rbase[2] = {reinterpret_cast<const char*>(rhof),
+                                       reinterpret_cast<const char*>(rhof + N)};
+  const char* __restrict__ lbase[2] = {reinterpret_cast<const char*>(lam),
+                                       reinterpret_cast<const char*>(lam + pg.sp)};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
     const uint32_t lb = links[i];
     if (lb & SELF_SOLID) {
@@ -127,29 +136,37 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       for (int d = 0; d < 3; ++d) j[a][d] = jm[(size_t)(3 * a + d) * N + i];
     }
     real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
-    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k;
-    // psi at every neighbour is kept for the parameter gradient
+    // lambda' of both species, requested before the neighbour densities so
+    // that all 74 loads of the node are in flight together
+    real lm[2][Q];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) lm[a][k] = ld_off<real>(lbase[a], (si + (uint32_t)k * PBLK) * SZ);
+    // S^a = sum_k W_k G^a(y) psi^b(y) c_k over the 18 neighbours y = x + c_k,
+    // and Wv = sum over the wall neighbours of W_k c_k (for the gradient of
+    // the wall parameters).  Every neighbour's densities are loaded (a wall
+    // node's field entry is a valid zero) and the wall content selected
+    // afterwards, so the loads carry no branch between them.
     real S[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    real pnb[Q][2];
+    real Wv[3] = {0, 0, 0};
+    real nA[Q], nB[Q];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const uint32_t yo = (uint32_t)nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]) * SZ;
+      nA[k] = ld_off<real>(rbase[0], yo);
+      nB[k] = ld_off<real>(rbase[1], yo);
+    }
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const bool wall = (lb >> k) & 1u;
-      real pA, pB;
-      if (wall) {
-        pA = ph.psiw[0];
-        pB = ph.psiw[1];
-      } else {
-        const int y = nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]);
-        pA = psi_of(ph.psi_form, rhof[y]);
-        pB = psi_of(ph.psi_form, rhof[(size_t)N + y]);
-      }
       const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-      const real eA = w * (wall ? ph.gw[0] : ph.gab) * pB;
-      const real eB = w * (wall ? ph.gw[1] : ph.gab) * pA;
+      const real eA = wall ? w * ph.gw[0] * ph.psiw[1] : w * ph.gab * psi_of(ph.psi_form, nB[k]);
+      const real eB = wall ? w * ph.gw[1] * ph.psiw[0] : w * ph.gab * psi_of(ph.psi_form, nA[k]);
+      const real wv = wall ? w : real(0);
+      Wv[0] += CX[k] * wv; Wv[1] += CY[k] * wv; Wv[2] += CZ[k] * wv;
       S[0][0] += CX[k] * eA; S[0][1] += CY[k] * eA; S[0][2] += CZ[k] * eA;
       S[1][0] += CX[k] * eB; S[1][1] += CY[k] * eB; S[1][2] += CZ[k] * eB;
-      pnb[k][0] = pA;
-      pnb[k][1] = pB;
     }
     real F[2][3];
     for (int a = 0; a < 2; ++a)
@@ -168,7 +185,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       const real uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        const real g = lam[a * (size_t)pg.sp + si + k * PBLK] * ph.inv_tau[a];
+        const real g = lm[a][k] * ph.inv_tau[a];
         const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
         const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
                        real(4.5) * s * s * s - real(4.5) * uu * s;
@@ -199,25 +216,19 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       for (int d = 0; d < 3; ++d) ef[(size_t)(a * 3 + d) * N + i] = dup[d] * f;
       drho[a] += -dupu * f;
     }
-    // transpose of the force: local part and parameter gradient
+    // transpose of the force: local part and the gradient of the wall
+    // parameters (the fluid neighbours' part, the g_ab gradient, is taken in
+    // the transposed stencil, which gathers the same pair products)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int b = 1 - a;
       const real dpsi_self = -(dF[a][0] * S[a][0] + dF[a][1] * S[a][1] + dF[a][2] * S[a][2]);
       for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi[a] * dF[a][d];
       df[(size_t)a * N + i] = drho[a] + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
-#pragma unroll
-      for (int k = 1; k < Q; ++k) {
-        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-        const real dFc = dF[a][0] * CX[k] + dF[a][1] * CY[k] + dF[a][2] * CZ[k];
-        const double t = (double)(-psi[a] * w * dFc);
-        if ((lb >> k) & 1u) {
-          gp[3 + a] += (double)ph.psiw[b] * t;
-          gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
-        } else {
-          gp[2] += (double)pnb[k][b] * t;
-        }
-      }
+      // sum over the wall neighbours of -psi^a W_k dF^a . c_k
+      const double t = (double)(-psi[a] * (dF[a][0] * Wv[0] + dF[a][1] * Wv[1] + dF[a][2] * Wv[2]));
+      gp[3 + a] += (double)ph.psiw[b] * t;
+      gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
     }
   }
   block_sum_adj<5>(gp, sh);
@@ -253,13 +264,24 @@ __device__ __forceinline__ void stencil_acc(const real* __restrict__ qf, int N,
   }
 }
 
+// The g_ab part of the parameter gradient, gathered with the stencil: the
+// local pass would add -psi^a(x) W_k dF^a(x) . c_k psi^b(y) for every fluid
+// pair (x, y = x + c_k); summed at y this is -psi^b(y) acc[b](y).  Each
+// workgroup writes (or, accumulating, adds) its sum to column GAB_COL of its
+// partials row.
+constexpr int GAB_COL = 5;
+
 template <typename real>
 __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict__ links,
                                                      const real* __restrict__ rhof, int nx, int ny,
                                                      int nz, Phys<real> ph,
                                                      const real* __restrict__ qf,
-                                                     real* __restrict__ df) {
+                                                     real* __restrict__ df,
+                                                     double* __restrict__ partials,
+                                                     int accumulate) {
+  __shared__ double sh[16];
   const int N = nx * ny * nz;
+  double gab[1] = {0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     if (links[i] & SELF_SOLID) continue;
     int xs[3], ys[3], zs[3];
@@ -269,9 +291,16 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
     real acc[2];
     stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-      df[(size_t)b * N + i] += dpsi_of(ph.psi_form, rhof[(size_t)b * N + i]) * (-ph.gab * acc[b]);
+    for (int b = 0; b < 2; ++b) {
+      const real rb = rhof[(size_t)b * N + i];
+      df[(size_t)b * N + i] += dpsi_of(ph.psi_form, rb) * (-ph.gab * acc[b]);
+      gab[0] -= (double)psi_of(ph.psi_form, rb) * (double)acc[b];
+    }
   }
+  block_sum_adj<1>(gab, sh);
+  if (threadIdx.x == 0)
+    partials[blockIdx.x * RED_STRIDE + GAB_COL] =
+        accumulate ? partials[blockIdx.x * RED_STRIDE + GAB_COL] + gab[0] : gab[0];
 }
 
 // Transposed streaming (FUSED: with the transposed force stencil in the same
@@ -292,7 +321,11 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
                                                     const real* __restrict__ qf,
                                                     const real* __restrict__ df,
                                                     const real* __restrict__ ef,
-                                                    real* __restrict__ out) {
+                                                    real* __restrict__ out,
+                                                    double* __restrict__ partials,
+                                                    int accumulate) {
+  __shared__ double sh[16];
+  double gab[1] = {0};
   const int N = nx * ny * nz;
   const PopGeo pg = pop_geo(nx, ny, nz);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
@@ -312,7 +345,11 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       real D = df[(size_t)a * N + i];
-      if constexpr (FUSED) D += dpsi_of(ph.psi_form, rhof[(size_t)a * N + i]) * (-ph.gab * acc[a]);
+      if constexpr (FUSED) {
+        const real ra = rhof[(size_t)a * N + i];
+        D += dpsi_of(ph.psi_form, ra) * (-ph.gab * acc[a]);
+        gab[0] -= (double)psi_of(ph.psi_form, ra) * (double)acc[a];
+      }
       const real Ex = ef[(size_t)(a * 3 + 0) * N + i];
       const real Ey = ef[(size_t)(a * 3 + 1) * N + i];
       const real Ez = ef[(size_t)(a * 3 + 2) * N + i];
@@ -333,6 +370,12 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
           oa[si + k * PBLK] = mu[OPP[k]];
       }
     }
+  }
+  if constexpr (FUSED) {
+    block_sum_adj<1>(gab, sh);
+    if (threadIdx.x == 0)
+      partials[blockIdx.x * RED_STRIDE + GAB_COL] =
+          accumulate ? partials[blockIdx.x * RED_STRIDE + GAB_COL] + gab[0] : gab[0];
   }
 }
 
@@ -360,15 +403,18 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
   }
   hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, jm,
                      lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
-  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   // FP64 adds the transposed stencil inside the push pass (one fewer sweep
-  // of D); in FP32 the gathers slow that pass more than the sweep costs
+  // of D); in FP32 the gathers slow that pass more than the sweep costs.
+  // The pass that gathers the stencil runs ADJ_BLOCKS workgroups, each with
+  // its row of g_ab partials.
   constexpr bool FUSED = sizeof(real) == 8;
+  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
   if (!FUSED)
-    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny,
-                       nz, ph, qf, df);
-  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(blocks), dim3(256), 0, s, links, nx, ny,
-                     nz, ph, lam_in, rhof, qf, df, ef, lam_out);
+    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(ADJ_BLOCKS), dim3(256), 0, s, links, rhof, nx,
+                       ny, nz, ph, qf, df, partials, accumulate);
+  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(FUSED ? ADJ_BLOCKS : blocks), dim3(256), 0,
+                     s, links, nx, ny, nz, ph, lam_in, rhof, qf, df, ef, lam_out, partials,
+                     accumulate);
   return hipGetLastError();
 }
 
@@ -413,6 +459,8 @@ __global__ __launch_bounds__(256) void k_sum5(const double* __restrict__ partial
   double v[5] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int j = 0; j < 5; ++j) v[j] += partials[b * RED_STRIDE + j];
+  // the g_ab part gathered with the transposed stencil (ADJ_BLOCKS rows)
+  for (int b = threadIdx.x; b < ADJ_BLOCKS; b += blockDim.x) v[2] += partials[b * RED_STRIDE + GAB_COL];
   block_sum_adj<5>(v, sh);
   if (threadIdx.x == 0)
     for (int j = 0; j < 5; ++j) {

@@ -155,6 +155,9 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  // lanes past the first column or row beyond a partial tile's edge feed
+  // no active node: they act as wall nodes (no pulls, never collided)
+  const bool need = (x0 + tx) <= nx && (y0 + ty) <= ny;
   int xs[3], ys[3];
   axis3(wrap_index(x0 + tx, nx), nx, xs);
   axis3(wrap_index(y0 + ty, ny), ny, ys);
@@ -169,12 +172,15 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
 #pragma unroll
   for (int h = 0; h < T::HPT; ++h) {
     const int q = tid + h * T::NT;
-    hval[h] = q < T::R;
+    const bool valid = q < T::R;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
     else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
     else { lx = TX; ly = q - 2 * T::LX - TY; }
+    // a halo node no active node of the tile reads (past the first column
+    // or row beyond a partial tile's edge) is left out: no loads, no e
+    hval[h] = valid && x0 + lx <= nx && y0 + ly <= ny;
     if (!hval[h]) { lx = 0; ly = 0; }
     axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
     axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
@@ -190,7 +196,7 @@ __device__ __forceinline__ void step_tile(const LatDev<real>& L, int bx, int by,
   uint32_t lbi, lbh[T::HPT];
   auto load_links = [&](int zr, uint32_t& li, uint32_t(&lh)[T::HPT]) {
     const int z = wrap_index(zr, nz);
-    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+    li = need ? L.links[(z * ny + ys[1]) * nx + xs[1]] : SELF_SOLID;
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h)
       lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
@@ -352,6 +358,9 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  // lanes past the first column or row beyond a partial tile's edge feed
+  // no active node: they act as wall nodes (no pulls, never collided)
+  const bool need = (x0 + tx) <= nx && (y0 + ty) <= ny;
   int xs[3], ys[3];
   axis3(wrap_index(x0 + tx, nx), nx, xs);
   axis3(wrap_index(y0 + ty, ny), ny, ys);
@@ -367,13 +376,16 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
     const int q = (sl >> 6) * 32 + (sl & 31);
-    hval[h] = q < T::R;
+    const bool valid = q < T::R;
     hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
     else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
     else { lx = TX; ly = q - 2 * T::LX - TY; }
+    // a halo node no active node of the tile reads (past the first column
+    // or row beyond a partial tile's edge) is left out: no loads, no e
+    hval[h] = valid && x0 + lx <= nx && y0 + ly <= ny;
     if (!hval[h]) { lx = 0; ly = 0; }
     axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
     axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
@@ -388,7 +400,7 @@ __device__ __forceinline__ void step_tile_split(const LatDev<real>& L, int bx, i
   uint32_t lbi, lbh[T::HPT];
   auto load_links = [&](int zr, uint32_t& li, uint32_t(&lh)[T::HPT]) {
     const int z = wrap_index(zr, nz);
-    li = L.links[(z * ny + ys[1]) * nx + xs[1]];
+    li = need ? L.links[(z * ny + ys[1]) * nx + xs[1]] : SELF_SOLID;
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h)
       lh[h] = hval[h] ? L.links[(z * ny + hy[h][1]) * nx + hx[h][1]] : SELF_SOLID;
@@ -619,6 +631,9 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
   const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  // lanes past the first column or row beyond a partial tile's edge feed
+  // no active node: they act as wall nodes (no pulls, never collided)
+  const bool need = (x0 + tx) <= nx && (y0 + ty) <= ny;
   int xs[3], ys[3];
   axis3(wrap_index(x0 + tx, nx), nx, xs);
   axis3(wrap_index(y0 + ty, ny), ny, ys);
@@ -635,13 +650,16 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
     const int q = (sl >> 6) * 32 + (sl & 31);
-    hval[h] = q < T::R;
+    const bool valid = q < T::R;
     hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
     else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
     else { lx = TX; ly = q - 2 * T::LX - TY; }
+    // a halo node no active node of the tile reads (past the first column
+    // or row beyond a partial tile's edge) is left out: no loads, no e
+    hval[h] = valid && x0 + lx <= nx && y0 + ly <= ny;
     if (!hval[h]) { lx = 0; ly = 0; }
     axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
     axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
@@ -670,7 +688,7 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
   auto zof = [&](int j) { return dir > 0 ? za - 1 + j : zb - j; };
   auto links_of = [&](int j, uint32_t& li, uint32_t(&lh)[T::HPT]) {
     const int zn = wrap_index(zof(j), nz) * nx * ny;
-    li = L.links[zn + cidx];
+    li = need ? L.links[zn + cidx] : SELF_SOLID;
 #pragma unroll
     for (int h = 0; h < T::HPT; ++h) lh[h] = hval[h] ? L.links[zn + hidx[h]] : SELF_SOLID;
   };
@@ -858,6 +876,9 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const bool active = (x0 + tx) < nx && (y0 + ty) < ny;
+  // lanes past the first column or row beyond a partial tile's edge feed
+  // no active node: they act as wall nodes (no pulls, never collided)
+  const bool need = (x0 + tx) <= nx && (y0 + ty) <= ny;
   int xs[3], ys[3];
   axis3(wrap_index(x0 + tx, nx), nx, xs);
   axis3(wrap_index(y0 + ty, ny), ny, ys);
@@ -871,13 +892,16 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
   for (int h = 0; h < T::HPT; ++h) {
     const int sl = tid + h * T::NT;
     const int q = (sl >> 6) * 32 + (sl & 31);
-    hval[h] = q < T::R;
+    const bool valid = q < T::R;
     hsp[h] = (sl >> 5) & 1;
     int lx, ly;
     if (q < T::LX) { ly = -1; lx = q - 1; }
     else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
     else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
     else { lx = TX; ly = q - 2 * T::LX - TY; }
+    // a halo node no active node of the tile reads (past the first column
+    // or row beyond a partial tile's edge) is left out: no loads, no e
+    hval[h] = valid && x0 + lx <= nx && y0 + ly <= ny;
     if (!hval[h]) { lx = 0; ly = 0; }
     axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
     axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
@@ -904,7 +928,7 @@ __device__ __forceinline__ void step_tile_pipe(const LatDev<real>& L, int bx, in
       if (!hw[h]) pull19(L.src, L.geo, hsp[h], hx[h], hy[h], zs, nx, lb, hm[h]);
     }
     const int i = (zs[1] * ny + ys[1]) * nx + xs[1];
-    const uint32_t lb = L.links[i];
+    const uint32_t lb = need ? L.links[i] : SELF_SOLID;
     solid_out = (lb & SELF_SOLID) != 0;
     if (!solid_out) pull19(L.src, L.geo, a, xs, ys, zs, nx, lb, nout);
   };
