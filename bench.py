@@ -277,6 +277,7 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     tile, _ = B.autotune(3, None)
+    members = B.member_tiles()
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     B.graph_capture(graph_steps)
@@ -322,7 +323,9 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
     return {"droplets": n, "fluid_nodes": nf, "dtype": "f32", "steps": steps,
             "graph_steps": graph_steps,
             "batched_mlups": round(nf / per_step_b / 1e6, 1),
-            "batched_tile": {"shape": list(tl[tile[0]]), "zchunk": tile[1], "grid": tile[2]},
+            "batched_tile": {"shape": list(tl[tile[0]]), "zchunk": tile[1], "grid": tile[2],
+                             "member_variants": {"x".join(map(str, tl[v])): sum(1 for m in members if m[0] == v)
+                                                 for v in sorted(set(m[0] for m in members))}},
             "sequential_tuned_mlups": round(nf / ts_tuned / 1e6, 1),
             "sequential_default_mlups": round(nf / ts_default / 1e6, 1),
             "sequential_default_steps": seq_default_steps,

@@ -368,24 +368,35 @@ scd_status scd_batch_lattice(scd_batch* b, int32_t i, scd_lattice** view);
 scd_status scd_batch_init_equilibrium(scd_batch* b, int32_t i, const double* d_rho_a,
                                       const double* d_rho_b);
 /* Step variant (see scd_tile_list), z-chunk (1 .. 32767 planes, else
- * SCD_EINVAL) and number of persistent workgroups (grid); grid 0 (the
- * default) launches one workgroup per (lattice, tile) item, a shorter grid
- * walks the items persistently (rounded up to a multiple of 8).  Items are
- * dealt to the 8 XCDs in contiguous ranges (the chunks of a tile column and
- * the columns of a lattice stay on one XCD), and neighbouring z-chunks march
- * in opposite directions, as in scd_step.  Defaults: the single-lattice
- * default variant of the dtype, 32-plane chunks, grid 0. */
+ * SCD_EINVAL) and number of persistent workgroups (grid), the same for every
+ * member; grid 0 (the default) launches one workgroup per (lattice, tile)
+ * item, a shorter grid walks the items persistently (rounded up to a
+ * multiple of 8).  Items are dealt to the 8 XCDs in contiguous ranges (the
+ * chunks of a tile column and the columns of a lattice stay on one XCD), and
+ * neighbouring z-chunks march in opposite directions, as in scd_step.
+ * Defaults: the single-lattice default variant of the dtype, 32-plane
+ * chunks, grid 0. */
 scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t grid);
+/* Variant and z-chunk of member i alone (the grid stays).  Members are
+ * stepped in groups of equal variant, one launch per group and step, each
+ * group's items dealt to the XCDs as above. */
+scd_status scd_batch_set_member_tile(scd_batch* b, int32_t i, int32_t variant, int32_t zc);
+scd_status scd_batch_member_tile(const scd_batch* b, int32_t i, int32_t* variant, int32_t* zc);
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps);
-/* Time every compiled variant x z-chunk {8, 16, 32, 64} x grid {one
- * workgroup per item, 4 per compute unit} for steps_per_trial steps (plus one
- * warm-up) and keep the fastest; h_best = {variant, zc, grid}, h_ms = its
+/* Pick the batch's tiles by timing: (1) every compiled variant for all
+ * members at 16- and 32-plane chunks, one workgroup per item; (2) for each
+ * member the variant that steps it alone fastest (each at the wave-count
+ * model's chunk for that lattice), then with those variants every chunk of
+ * {8, 16, 32, 48, 64} x grid {one workgroup per item, 4 per compute unit};
+ * the fastest of all is kept.  A trial is steps_per_trial steps (plus one
+ * warm-up); h_best = {the most common member variant, zc, grid}, h_ms its
  * time per step.  The members advance by every trial step (re-initialise
  * afterwards for a clean start).  cache_path (or NULL): JSON-lines file; a
- * line with the same key (member shapes, dtype, device, variant count) is
- * used without timing, a new result is appended.  Drops a captured graph. */
+ * line with the same key (member shapes, dtype, device, variant count) and
+ * its member variants is used without timing, a new result is appended.
+ * Drops a captured graph. */
 scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
                               int32_t* h_best, double* h_ms);
 

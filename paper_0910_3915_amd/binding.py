@@ -106,6 +106,8 @@ _PROTOS = {
     "scd_batch_lattice": [_VP, _I32, ctypes.POINTER(_VP)],
     "scd_batch_init_equilibrium": [_VP, _I32, _VP, _VP],
     "scd_batch_set_tile": [_VP, _I32, _I32, _I32],
+    "scd_batch_set_member_tile": [_VP, _I32, _I32, _I32],
+    "scd_batch_member_tile": [_VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
     "scd_batch_step": [_VP, _I64],
     "scd_batch_graph_capture": [_VP, _I64],
     "scd_batch_graph_replay": [_VP, _I64],
@@ -527,6 +529,18 @@ class Batch:
 
     def set_tile(self, variant, zc, grid):
         check(lib().scd_batch_set_tile(self.h, int(variant), int(zc), int(grid)))
+
+    def set_member_tile(self, i, variant, zc):
+        check(lib().scd_batch_set_member_tile(self.h, int(i), int(variant), int(zc)))
+
+    def member_tiles(self):
+        """[(variant, zc)] of every member."""
+        out = []
+        for i in range(self.n):
+            v, z = _I32(), _I32()
+            check(lib().scd_batch_member_tile(self.h, i, ctypes.byref(v), ctypes.byref(z)))
+            out.append((v.value, z.value))
+        return out
 
     def step(self, n=1):
         check(lib().scd_batch_step(self.h, int(n)))

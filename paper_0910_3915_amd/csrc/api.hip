@@ -982,8 +982,13 @@ struct scd_batch {
   size_t desc_off[2];  // descriptor tables for even and odd parity
   size_t items_off;
   int nitems;
-  int variant, zc, grid;
-  int remap;  // XCD-contiguous ranges of the work list
+  int variant, zc, grid;  // the last uniform setting (scd_batch_set_tile)
+  int remap;              // XCD-contiguous ranges of the work list
+  std::vector<int> mvar, mzc;  // per member: step variant and z-chunk
+  struct Group {
+    int variant, start, count;  // a run of items that share one variant
+  };
+  std::vector<Group> groups;
   hipStream_t stream;
   int parity;
   hipGraph_t graph;
@@ -1018,14 +1023,17 @@ BatchLayout batch_layout(int n, const scd_params* p) {
   const size_t ds = latdev_size(p[0].dtype);
   L.desc[0] = off; off += align256(ds * n);
   L.desc[1] = off; off += align256(ds * n);
-  // room for the largest item list any compiled tile shape can produce
+  // room for the largest item list: every member with the compiled tile
+  // shape that cuts it into the most items, at one plane per chunk
   int maxitems = 0;
-  for (int t = 0; t < variant_count(); ++t) {
-    int a, b, v, w;
-    variant_at(t, &a, &b, &v, &w);
+  for (int i = 0; i < n; ++i) {
     int m = 0;
-    for (int i = 0; i < n; ++i) m += batch_items_of(p[i], a, b, 1);
-    maxitems = std::max(maxitems, m);
+    for (int t = 0; t < variant_count(); ++t) {
+      int a, b, v, w;
+      variant_at(t, &a, &b, &v, &w);
+      m = std::max(m, batch_items_of(p[i], a, b, 1));
+    }
+    maxitems += m;
   }
   L.items = off; off += align256((size_t)maxitems * 16);
   L.total = off;
@@ -1033,22 +1041,34 @@ BatchLayout batch_layout(int n, const scd_params* p) {
 }
 
 scd_status batch_upload(scd_batch* b) {
-  // descriptors for both parities and the (lattice, tile) work list
+  // descriptors for both parities and the (lattice, tile) work list; the
+  // members are taken in order of their step variant, so that the items of
+  // one variant form one contiguous group (one launch per group and step)
   const size_t ds = latdev_size(b->dtype);
   std::vector<char> d0(ds * b->n), d1(ds * b->n);
   std::vector<int32_t> items;
+  std::vector<int> order(b->n);
+  for (int i = 0; i < b->n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->mvar[x] < b->mvar[y]; });
+  b->groups.clear();
   for (int i = 0; i < b->n; ++i) {
     scd_lattice* v = b->views[i];
     latdev_fill(b->dtype, d0.data() + ds * i, v->pop[0], v->pop[1], v->links(), v->p.nx, v->p.ny,
                 v->p.nz, v->ph);
     latdev_fill(b->dtype, d1.data() + ds * i, v->pop[1], v->pop[0], v->links(), v->p.nx, v->p.ny,
                 v->p.nz, v->ph);
-    const int zc = std::min(b->zc, v->p.nz);
+  }
+  for (int i : order) {
+    scd_lattice* v = b->views[i];
+    const int zc = std::min(b->mzc[i], v->p.nz);
     if (zc > 32767) return fail(SCD_EINVAL, "z-chunk %d exceeds 32767 planes", zc);
     int tx, ty, var, wpe;
-    variant_at(b->variant, &tx, &ty, &var, &wpe);
+    variant_at(b->mvar[i], &tx, &ty, &var, &wpe);
     const int gx = (v->p.nx + tx - 1) / tx, gy = (v->p.ny + ty - 1) / ty;
     const int gz = (v->p.nz + zc - 1) / zc;
+    const int start = (int)(items.size() / 4);
+    if (b->groups.empty() || b->groups.back().variant != b->mvar[i])
+      b->groups.push_back({b->mvar[i], start, 0});
     // chunks of a column adjacent, then the columns along x, then y; even
     // chunks march down and odd ones up, so that two neighbouring chunks
     // reach their shared boundary planes together (as in the single-lattice
@@ -1063,6 +1083,7 @@ scd_status batch_upload(scd_batch* b) {
           items.push_back(by);
           items.push_back((int32_t)((uint32_t)za | ((uint32_t)zlen << 16) | (down ? 0x80000000u : 0u)));
         }
+    b->groups.back().count += (int)(items.size() / 4) - start;
   }
   b->nitems = (int)(items.size() / 4);
   HIPCHK(hipMemcpyAsync(b->arena + b->desc_off[0], d0.data(), d0.size(), hipMemcpyHostToDevice, b->stream));
@@ -1094,13 +1115,17 @@ void batch_drop_graph(scd_batch* b) {
 
 scd_status batch_enqueue(scd_batch* b, int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
-    // one workgroup per item, or a persistent grid (a multiple of 8 with
-    // the XCD remap, so that each block stays on one XCD's range)
-    const int slots = b->remap ? 8 * ((b->nitems + 7) / 8) : b->nitems;
-    int grid = (b->grid <= 0 || b->grid > slots) ? slots : b->grid;
-    if (b->remap) grid = 8 * ((grid + 7) / 8);
-    HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity], b->arena + b->items_off,
-                             b->nitems, grid, b->variant, b->remap, b->stream));
+    // one launch per variant group: one workgroup per item, or a persistent
+    // grid (a multiple of 8 with the XCD remap, so that each block stays on
+    // one XCD's range)
+    for (const auto& g : b->groups) {
+      const int slots = b->remap ? 8 * ((g.count + 7) / 8) : g.count;
+      int grid = (b->grid <= 0 || b->grid > slots) ? slots : b->grid;
+      if (b->remap) grid = 8 * ((grid + 7) / 8);
+      HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity],
+                               b->arena + b->items_off + (size_t)g.start * 16, g.count, grid,
+                               g.variant, b->remap, b->stream));
+    }
     b->parity ^= 1;
     for (scd_lattice* v : b->views) {
       v->cur = b->parity;
@@ -1142,6 +1167,8 @@ scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const
   b->items_off = L.items;
   batch_default_tile(p[0].dtype, &b->variant, &b->zc, &b->grid);
   b->remap = 1;
+  b->mvar.assign(n, b->variant);
+  b->mzc.assign(n, b->zc);
   b->stream = (hipStream_t)stream;
   b->parity = 0;
   b->graph = nullptr;
@@ -1201,9 +1228,31 @@ scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t
   b->variant = variant;
   b->zc = zc;
   b->grid = grid;
+  b->mvar.assign(b->n, variant);
+  b->mzc.assign(b->n, zc);
   for (scd_lattice* v : b->views) { v->variant = variant; v->zc = std::min(zc, v->p.nz); }
   batch_drop_graph(b);
   return batch_upload(b);
+}
+
+scd_status scd_batch_set_member_tile(scd_batch* b, int32_t i, int32_t variant, int32_t zc) {
+  if (!b || i < 0 || i >= b->n) return fail(SCD_EINVAL, "bad batch index");
+  if (variant < 0 || variant >= variant_count())
+    return fail(SCD_EINVAL, "variant %d is not compiled", variant);
+  if (zc < 1 || zc > 32767) return fail(SCD_EINVAL, "z-chunk must be in [1, 32767]");
+  b->mvar[i] = variant;
+  b->mzc[i] = zc;
+  b->views[i]->variant = variant;
+  b->views[i]->zc = std::min(zc, b->views[i]->p.nz);
+  batch_drop_graph(b);
+  return batch_upload(b);
+}
+
+scd_status scd_batch_member_tile(const scd_batch* b, int32_t i, int32_t* variant, int32_t* zc) {
+  if (!b || i < 0 || i >= b->n || !variant || !zc) return fail(SCD_EINVAL, "bad argument");
+  *variant = b->mvar[i];
+  *zc = b->mzc[i];
+  return SCD_OK;
 }
 
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps) {
@@ -1235,6 +1284,33 @@ scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps) {
   return SCD_OK;
 }
 
+// Per-member variants of a cached batch tuning: the "members" list of the
+// last line whose key matches (empty when there is none).
+static std::vector<int> cache_members(const char* path, const std::string& key) {
+  std::vector<int> out;
+  if (!path) return out;
+  std::ifstream f(path);
+  std::string line;
+  const std::string k = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(k) == std::string::npos) continue;
+    const char* m = strstr(line.c_str(), "\"members\": [");
+    if (!m) continue;
+    std::vector<int> v;
+    const char* c = m + strlen("\"members\": [");
+    while (*c && *c != ']') {
+      char* e = nullptr;
+      const long x = strtol(c, &e, 10);
+      if (e == c) break;
+      v.push_back((int)x);
+      c = e;
+      while (*c == ',' || *c == ' ') ++c;
+    }
+    out = v;
+  }
+  return out;
+}
+
 scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
                               int32_t* best, double* best_ms) {
   if (!b || !best || !best_ms) return fail(SCD_EINVAL, "NULL argument");
@@ -1245,57 +1321,141 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
     for (int d : {v->p.nx, v->p.ny, v->p.nz}) hsh = (hsh ^ (uint64_t)d) * 1099511628211ull;
   std::ostringstream ko;
   ko << "batch" << b->n << ":" << std::hex << hsh << std::dec << ":" << (b->dtype == SCD_F64 ? "f64" : "f32")
-     << ":" << device_name() << ":v" << variant_count();
+     << ":" << device_name() << ":v" << variant_count() << ":members";
   const std::string key = ko.str();
   int cached[3];
   double cms;
   if (cache_lookup3(cache_path, key, cached, &cms) && cached[0] >= 0 && cached[0] < variant_count()) {
-    scd_status st = scd_batch_set_tile(b, cached[0], cached[1], cached[2]);
-    if (st) return st;
-    for (int j = 0; j < 3; ++j) best[j] = cached[j];
-    *best_ms = cms;
-    return SCD_OK;
+    const std::vector<int> mv = cache_members(cache_path, key);
+    if ((int)mv.size() == b->n) {
+      for (int v : mv)
+        if (v < 0 || v >= variant_count()) return fail(SCD_EINVAL, "bad cached variant %d", v);
+      b->mvar = mv;
+      b->mzc.assign(b->n, cached[1]);
+      b->variant = cached[0];
+      b->zc = cached[1];
+      b->grid = cached[2];
+      for (int i = 0; i < b->n; ++i) {
+        b->views[i]->variant = mv[i];
+        b->views[i]->zc = std::min(cached[1], b->views[i]->p.nz);
+      }
+      batch_drop_graph(b);
+      scd_status st = batch_upload(b);
+      if (st) return st;
+      for (int j = 0; j < 3; ++j) best[j] = cached[j];
+      *best_ms = cms;
+      return SCD_OK;
+    }
   }
   const int cus = device_cus();
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  auto time_batch = [&](double* per) -> scd_status {
+    scd_status st = batch_enqueue(b, 1);  // warm-up
+    if (st) return st;
+    HIPCHK(hipEventRecord(e0, b->stream));
+    st = batch_enqueue(b, steps_per_trial);
+    if (st) return st;
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *per = ms / steps_per_trial;
+    return SCD_OK;
+  };
+  // (1) one variant for all members: every compiled variant at 16- and
+  // 32-plane chunks, one workgroup per item
   double bms = 1e30;
   int bb[3] = {b->variant, b->zc, b->grid};
-  const int zcs[] = {8, 16, 32, 64};
-  const int grids[] = {0, 4 * cus};
+  std::vector<int> bmem(b->n, b->variant);
   for (int i = 0; i < variant_count(); ++i)
-    for (int zc : zcs)
-      for (int grid : grids) {
-        scd_status st = scd_batch_set_tile(b, i, zc, grid);
-        if (st) return st;
-        st = batch_enqueue(b, 1);  // warm-up
-        if (st) return st;
-        HIPCHK(hipEventRecord(e0, b->stream));
-        st = batch_enqueue(b, steps_per_trial);
-        if (st) return st;
-        HIPCHK(hipEventRecord(e1, b->stream));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        const double per = ms / steps_per_trial;
-        if (per < bms) {
-          bms = per;
-          bb[0] = i;
-          bb[1] = zc;
-          bb[2] = grid;
-        }
+    for (int zc : {16, 32}) {
+      scd_status st = scd_batch_set_tile(b, i, zc, 0);
+      if (st) return st;
+      double per;
+      st = time_batch(&per);
+      if (st) return st;
+      if (per < bms) {
+        bms = per;
+        bb[0] = i; bb[1] = zc; bb[2] = 0;
+        bmem.assign(b->n, i);
       }
+    }
+  // (2) a variant per member: the fastest on the member stepped alone (each
+  // variant at the z-chunk the wave-count model gives it for that lattice,
+  // over an even number of steps, so that the member keeps the batch's buffer
+  // parity), then the batch-wide chunk and grid for those variants
+  const int trial = 2 * ((steps_per_trial + 1) / 2);
+  std::vector<int> mv(b->n);
+  for (int m = 0; m < b->n; ++m) {
+    scd_lattice* v = b->views[m];
+    double best_t = 1e30;
+    mv[m] = bb[0];
+    for (int i = 0; i < variant_count(); ++i) {
+      int tx, ty, var, wpe;
+      variant_at(i, &tx, &ty, &var, &wpe);
+      if (tx > 2 * v->p.nx && tx > 16) continue;  // mostly idle lanes
+      v->variant = i;
+      v->zc = default_zc(v->p, i);
+      scd_status st = enqueue_steps(v, 2);
+      if (st) return st;
+      HIPCHK(hipEventRecord(e0, b->stream));
+      st = enqueue_steps(v, trial);
+      if (st) return st;
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_t) {
+        best_t = ms;
+        mv[m] = i;
+      }
+    }
+  }
+  for (int zc : {8, 16, 32, 48, 64})
+    for (int grid : {0, 4 * cus}) {
+      b->mvar = mv;
+      b->mzc.assign(b->n, zc);
+      b->grid = grid;
+      batch_drop_graph(b);
+      scd_status st = batch_upload(b);
+      if (st) return st;
+      double per;
+      st = time_batch(&per);
+      if (st) return st;
+      if (per < bms) {
+        bms = per;
+        int cnt[64] = {0}, top = mv[0];
+        for (int x : mv)
+          if (x < 64 && ++cnt[x] > cnt[top]) top = x;
+        bb[0] = top; bb[1] = zc; bb[2] = grid;
+        bmem = mv;
+      }
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  scd_status st = scd_batch_set_tile(b, bb[0], bb[1], bb[2]);
+  // apply the fastest
+  b->mvar = bmem;
+  b->mzc.assign(b->n, bb[1]);
+  b->variant = bb[0];
+  b->zc = bb[1];
+  b->grid = bb[2];
+  for (int i = 0; i < b->n; ++i) {
+    b->views[i]->variant = bmem[i];
+    b->views[i]->zc = std::min(bb[1], b->views[i]->p.nz);
+  }
+  batch_drop_graph(b);
+  scd_status st = batch_upload(b);
   if (st) return st;
   for (int j = 0; j < 3; ++j) best[j] = bb[j];
   *best_ms = bms;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"best\": [" << bb[0] << ", " << bb[1] << ", " << bb[2]
-      << "], \"ms\": " << std::setprecision(17) << bms << "}\n";
+      << "], \"members\": [";
+    for (int i = 0; i < b->n; ++i) f << (i ? ", " : "") << bmem[i];
+    f << "], \"ms\": " << std::setprecision(17) << bms << "}\n";
   }
   return SCD_OK;
 }

@@ -73,6 +73,33 @@ def test_batch_members_against_oracle(dtype):
         assert d <= bound, (i, d)
 
 
+def test_mixed_member_tiles_equal_sequential():
+    """Members with different step variants and chunks (three launch groups
+    per step) evolve bit for bit as each lattice stepped alone with its own
+    tile, eagerly and from a captured graph."""
+    announce("batch: 3 members with three different variants, f32, 30 steps")
+    cases = _members("f32")
+    tl = scd.tile_list()
+    picks = [scd.variant_index(64, 4, 6, 2), scd.variant_index(32, 8, 0, 1), scd.variant_index(32, 4, 7, 1)]
+    zcs = [8, 5, 20]
+    s = torch.cuda.Stream()
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+        B.set_member_tile(i, picks[i], zcs[i])
+    assert B.member_tiles() == list(zip(picks, zcs))
+    B.step(10)
+    B.graph_capture(10)
+    B.graph_replay(2)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        L = scd.Lattice(c["params"], c["solid"])
+        L.set_tile(picks[i], min(zcs[i], c["params"]["nz"]))
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(30)
+        assert torch.equal(B.view(i).get_state().cpu(), L.get_state().cpu()), (i, tl[picks[i]])
+
+
 def test_autotune_keeps_results(tmp_path):
     c = W.droplet_case(48, 40, 24, 9.0, 0.12, 0.1)
     L = scd.Lattice(c["params"], c["solid"])
@@ -101,14 +128,16 @@ def test_batch_autotune_then_default_tiles_match_sequential(tmp_path):
     cache = str(tmp_path / "btune.jsonl")
     best, ms = B.autotune(2, cache)
     assert ms > 0 and len(best) == 3
+    members = B.member_tiles()
     assert B.autotune(2, cache) == (best, ms)  # served from the cache
+    assert B.member_tiles() == members
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     B.step(24)
     torch.cuda.synchronize()
     for i, c in enumerate(cases):
         L = scd.Lattice(c["params"], c["solid"])
-        L.set_tile(best[0], min(best[1], c["params"]["nz"]))
+        L.set_tile(members[i][0], min(members[i][1], c["params"]["nz"]))
         L.init_equilibrium(c["rho_a"], c["rho_b"])
         L.step(24)
         assert torch.equal(B.view(i).get_state().cpu(), L.get_state().cpu()), i
@@ -130,6 +159,7 @@ def test_full_batch_sweep_equals_sequential():
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     best, _ = B.autotune(3, None)
+    members = B.member_tiles()
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     B.graph_capture(20)
@@ -141,7 +171,7 @@ def test_full_batch_sweep_equals_sequential():
         assert v.step_count == 20, i
         got = v.get_state()
         L = scd.Lattice(c["params"], c["solid"], stream=s)
-        L.set_tile(best[0], min(best[1], c["params"]["nz"]))
+        L.set_tile(members[i][0], min(members[i][1], c["params"]["nz"]))
         L.init_equilibrium(c["rho_a"], c["rho_b"])
         L.step(20)
         assert torch.equal(got, L.get_state()), i
