@@ -13,7 +13,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same source (the sanitizer build of
+# the sanitized test run); by default the optimised liboracle.so
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 CA_NO_REF = 1
 CA_E1_FLAT = 2
@@ -67,6 +69,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
+            if "ORACLE_LIB" in os.environ:
+                raise FileNotFoundError(_LIB_PATH)
             build()
         L = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
