@@ -151,20 +151,28 @@ def autotuned_tile(scd, W, dtype, stream):
 
 
 def fp32_vs_fp64(scd, W, torch, steps, tile64, tile32, stream):
-    """The throughput run for `steps` steps in FP64, in FP32, and in FP64 with
+    """The throughput run for `steps` steps in FP64, in FP32, in FP64 with
     the state rounded to FP32 after every step (FP64 arithmetic, FP32
-    storage): the last shows how far rounding at the FP32 level alone moves
-    the densities over the run, next to the FP32 run's difference."""
+    storage), and in FP64 from initial densities perturbed by 6e-8 relative
+    (uniform, seeded): the last two show how far rounding at the FP32 level
+    alone, once per step or once at the start, moves the densities over the
+    run, next to the FP32 run's difference."""
     import numpy as np
     out = {}
     dens = {}
     mass = {}
-    for name, dt, tile in (("f64", "f64", tile64), ("f32", "f32", tile32), ("f64_f32_storage", "f64", tile64)):
+    for name, dt, tile in (("f64", "f64", tile64), ("f32", "f32", tile32), ("f64_f32_storage", "f64", tile64),
+                           ("f64_perturbed", "f64", tile64)):
         c = W.config_throughput(delta=0.2, dtype=dt)
         L = scd.Lattice(c["params"], c["solid"], stream=stream)
         if tile is not None:
             L.set_tile(*tile)
-        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        ra, rb = c["rho_a"], c["rho_b"]
+        if name == "f64_perturbed":
+            rng = np.random.default_rng(7)
+            ra = ra * (1.0 + 6e-8 * rng.uniform(-1.0, 1.0, ra.shape))
+            rb = rb * (1.0 + 6e-8 * rng.uniform(-1.0, 1.0, rb.shape))
+        L.init_equilibrium(ra, rb)
         m0 = L.observables()["mass"]
         if name == "f64_f32_storage":
             buf = L.empty_blocked()
@@ -183,6 +191,7 @@ def fp32_vs_fp64(scd, W, torch, steps, tile64, tile32, stream):
     return {"steps": steps,
             "max_abs_drho": float(np.max(np.abs(dens["f64"] - dens["f32"]))),
             "max_abs_drho_f64_f32_storage": float(np.max(np.abs(dens["f64"] - dens["f64_f32_storage"]))),
+            "max_abs_drho_f64_perturbed_6e-8": float(np.max(np.abs(dens["f64"] - dens["f64_perturbed"]))),
             "theta_e1_f64": out["f64"]["theta_e1"], "theta_e1_f32": out["f32"]["theta_e1"],
             "theta_e2_f64": out["f64"]["theta_e2"], "theta_e2_f32": out["f32"]["theta_e2"],
             "dtheta_e1": abs(out["f64"]["theta_e1"] - out["f32"]["theta_e1"]),
@@ -262,13 +271,14 @@ def _angles(lat, cfg):
 def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, seq_default_steps=200,
                           n=64):
     """The batched parameter sweep: 64 FP32 droplets drawn from seed 0, run
-    for `steps` steps in one batched launch per step (tiles picked by the
-    batch autotuner, a captured graph of graph_steps steps replayed), against
-    the same 64 droplets run one after another, one launch per step each,
-    with each lattice's autotuned tile for the same number of steps (and,
-    for the rate only, with the library's default tile over
-    seq_default_steps).  Both sides start from the same seeded state; the
-    contact angles of every droplet at the end are compared."""
+    for `steps` steps by the batch (tiles and cache-blocking sets picked by
+    the batch autotuner, a captured graph of graph_steps steps replayed),
+    against the same 64 droplets run one after another, one launch per step
+    each, with each lattice's autotuned tile for the same number of steps
+    (and, for the rate only, with the library's default tile over
+    seq_default_steps, both one lattice at a time and all lattices in turn
+    every step).  Both sides start from the same seeded state; the contact
+    angles of every droplet at the end are compared."""
     draws = W.batch_draw(n, seed=0)
     cases = [W.droplet_case(d["nx"], d["ny"], d["nz"], d["radius"], d["g_ab"], d["delta"], dtype="f32")
              for d in draws]
@@ -276,8 +286,9 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
     B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=stream)
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
-    tile, _ = B.autotune(3, None)
+    tile, _ = B.autotune(6, None)
     members = B.member_tiles()
+    set_bytes, nsets = B.blocking()
     for i, c in enumerate(cases):
         B.init_equilibrium(i, c["rho_a"], c["rho_b"])
     B.graph_capture(graph_steps)
@@ -312,6 +323,14 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
     lats = fresh(False)
     timed_runs(lats, 2)  # warm-up
     ts_default = timed_runs(lats, seq_default_steps) / seq_default_steps
+    # the same lattices advanced in turn, one launch each per step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(seq_default_steps):
+        for L in lats:
+            L.step(1)
+    torch.cuda.synchronize()
+    ts_inter = (time.perf_counter() - t0) / seq_default_steps
     lats = fresh(True)
     ts_tuned = timed_runs(lats, steps) / steps
     th_s = [_angles(L, c["ca"]) for L, c in zip(lats, cases)]
@@ -324,11 +343,13 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
             "graph_steps": graph_steps,
             "batched_mlups": round(nf / per_step_b / 1e6, 1),
             "batched_tile": {"shape": list(tl[tile[0]]), "zchunk": tile[1], "grid": tile[2],
+                             "set_bytes": set_bytes, "sets": nsets,
                              "member_variants": {"x".join(map(str, tl[v])): sum(1 for m in members if m[0] == v)
                                                  for v in sorted(set(m[0] for m in members))}},
             "sequential_tuned_mlups": round(nf / ts_tuned / 1e6, 1),
             "sequential_default_mlups": round(nf / ts_default / 1e6, 1),
             "sequential_default_steps": seq_default_steps,
+            "sequential_interleaved_mlups": round(nf / ts_inter / 1e6, 1),
             "speedup": round(min(ts_default, ts_tuned) / per_step_b, 3),
             "theta": {"droplets_compared": len(both),
                       "no_droplet_both": sum(1 for a, b in zip(th_b, th_s) if a is None and b is None),

@@ -67,6 +67,7 @@ typedef int32_t scd_status;
 #define SCD_ENONFINITE (-3)    /* NaN or Inf in the state */
 #define SCD_ENOINTERFACE (-4)  /* no droplet on the measurement column */
 #define SCD_EUNSUPPORTED (-5)  /* valid request this build cannot serve */
+#define SCD_EDRIFT (-6)        /* mass drifted beyond the watchdog tolerance */
 
 #define SCD_F64 0
 #define SCD_F32 1
@@ -240,8 +241,23 @@ double scd_huang_angle(const scd_params* p, double rho_in, double rho_out);
 
 /* Mass per species, total momentum and the all-finite flag, accumulated in
  * FP64 with a fixed reduction order (bit-reproducible).  Synchronises.
- * Returns SCD_ENONFINITE (with *out filled) if any population is not finite. */
+ * Returns SCD_ENONFINITE (with *out filled) if any population is not finite,
+ * else SCD_EDRIFT (with *out filled) when the mass-drift watchdog is on and
+ * either species' mass has drifted beyond its tolerance. */
 scd_status scd_observables(scd_lattice* h, scd_obs* h_out);
+/* Mass-drift watchdog (failure detection; the method conserves each
+ * species' mass exactly, so any drift is rounding or a fault).  The
+ * reference masses are those of the first scd_observables call after the
+ * state was last set (scd_init_equilibrium, scd_set_state, scd_fill_state);
+ * every later call measures (m_a - m_a,ref) / m_a,ref.  rel_tol 0 (the
+ * default) only measures; rel_tol > 0 makes scd_observables return
+ * SCD_EDRIFT when |drift| exceeds it for either species.  Setting the
+ * tolerance keeps the reference.  Suggested tolerances: 1e-10 in FP64,
+ * 1e-5 in FP32.  rel_tol < 0 or NaN: SCD_EINVAL. */
+scd_status scd_set_mass_watchdog(scd_lattice* h, double rel_tol);
+/* The relative drift of both species at the last scd_observables call
+ * (h_drift: host array of 2; 0 at the call that took the reference). */
+scd_status scd_mass_drift(const scd_lattice* h, double* h_drift);
 
 /* Contact angle of the current state (Sec. 3), both estimators.
  * Synchronises.  Returns SCD_ENOINTERFACE with NaN angles and
@@ -287,7 +303,8 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
  * (deg).  The parameters are constants of the run; the gradient is taken
  * over these nsteps steps only.
  * Backward (one level): for each segment in reverse, recomputes its states
- * into d_seg (ckpt_every buffers; each recomputed step writes its slot
+ * into d_seg (scd_ckpt_seg_states buffers: ckpt_every - 1, or 2 when the
+ * moment cache covers the segment; each recomputed step writes its slot
  * directly) and applies the adjoint steps; d_lam holds 2 population buffers
  * of scratch.  h_grad[5] = dL/d{rho_wall_A, rho_wall_B, g_ab, g_wall_A,
  * g_wall_B}.  Needs the state left by the forward call; on return the
@@ -295,9 +312,11 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc);
  * from).
  * Backward (two levels): inside each level-1 segment, recomputes level-2
  * checkpoints every K2 steps into d_mid (ceil(K1 / K2) buffers) and runs the
- * one-level sweep on each sub-segment with d_seg of K2 buffers: each step is
- * recomputed twice and the memory is ceil(n/K1) + ceil(K1/K2) + K2 + 2
- * states instead of ceil(n/K) + K + 2. */
+ * one-level sweep on each sub-segment with d_seg of scd_ckpt_seg_states(K2)
+ * buffers: each step is recomputed twice and the memory is ceil(n/K1) +
+ * ceil(K1/K2) + K2 + 1 states instead of ceil(n/K) + K + 1 (with the moment
+ * cache: + 2 states + the cached moments, 8 x N reals per step of a
+ * segment, instead of + K2 - 1 or K - 1 states). */
 scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
                             int64_t nsteps, int64_t ckpt_every, void* d_ckpt,
                             const scd_ca_cfg* cfg, double target_deg, double* h_out);
@@ -310,8 +329,13 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
  * post-stream populations of the state it reads, and the adjoint of that
  * state uses them instead of pulling its populations to form them.  These
  * are the same sums in the same order, so the gradient is the same bit for
- * bit. */
+ * bit.  Such an adjoint reads nothing else of its state, so the recomputed
+ * states then alternate between two buffers of d_seg. */
 scd_status scd_ckpt_moment_cache(scd_lattice* h, void* d_buf, int64_t nsteps);
+/* Population buffers d_seg must hold for segments of seg_len steps with the
+ * lattice's current step variant and moment cache: 2 (at most seg_len - 1)
+ * when the cache covers the segment, else seg_len - 1 (0 for seg_len 1). */
+scd_status scd_ckpt_seg_states(const scd_lattice* h, int64_t seg_len, int64_t* h_states);
 scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t ckpt_every,
                              const void* d_ckpt, void* d_seg, void* d_lam,
                              const scd_ca_cfg* cfg, double target_deg, double* h_grad);
@@ -351,12 +375,14 @@ scd_status scd_graph_capture(scd_lattice* h, int64_t nsteps);
 scd_status scd_graph_replay(scd_lattice* h, int64_t reps);
 
 /* ---- batched launch (extension) ----
- * n lattices of any sizes (one dtype) advance together: each step is one
- * persistent launch whose workgroups walk a list of (lattice, tile) items.
- * The caller provides one device arena of scd_batch_sizes bytes that holds
- * every lattice's two population buffers and work area, the per-lattice
- * descriptors and the work list.  d_solid: host array of n device pointers
- * to the solid masks (kept alive by the caller). */
+ * n lattices of any sizes (one dtype) advance together: a step is one
+ * launch per group of members (members of one step variant, at most 16 per
+ * launch, whose descriptors travel in the kernel arguments), whose
+ * workgroups walk the members' (tile column, z-chunk) items; a group of one
+ * member with one workgroup per item is launched as scd_step launches it.  The caller provides one
+ * device arena of scd_batch_sizes bytes that holds every lattice's two
+ * population buffers and work area and the work list.  d_solid: host array
+ * of n device pointers to the solid masks (kept alive by the caller). */
 typedef struct scd_batch scd_batch;
 scd_status scd_batch_sizes(int32_t n, const scd_params* p, size_t* arena_bytes);
 scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const* d_solid,
@@ -382,20 +408,37 @@ scd_status scd_batch_set_tile(scd_batch* b, int32_t variant, int32_t zc, int32_t
  * group's items dealt to the XCDs as above. */
 scd_status scd_batch_set_member_tile(scd_batch* b, int32_t i, int32_t variant, int32_t zc);
 scd_status scd_batch_member_tile(const scd_batch* b, int32_t i, int32_t* variant, int32_t* zc);
+/* Cache blocking across members: the members are packed, in index order,
+ * into sets whose state (both population buffers and the link masks) stays
+ * within set_bytes (a member larger than that forms a set alone), and
+ * scd_batch_step, like a captured graph, runs every step of a call on one
+ * set before it moves to the next.  A set's state then stays in the 256 MB
+ * last-level cache (MALL) between its steps instead of being evicted by the
+ * other members' traffic.  The members are independent, so the result is
+ * the same for any set_bytes.  0 (the default) makes one set of all members,
+ * which advance one step per launch.  set_bytes < 0: SCD_EINVAL.  Drops a
+ * captured graph.  scd_batch_blocking returns the setting and the number of
+ * sets it gives. */
+scd_status scd_batch_set_blocking(scd_batch* b, int64_t set_bytes);
+scd_status scd_batch_blocking(const scd_batch* b, int64_t* set_bytes, int32_t* nsets);
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps);
 scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps);
-/* Pick the batch's tiles by timing: (1) every compiled variant for all
- * members at 16- and 32-plane chunks, one workgroup per item; (2) for each
- * member the variant that steps it alone fastest (each at the wave-count
- * model's chunk for that lattice), then with those variants every chunk of
- * {8, 16, 32, 48, 64} x grid {one workgroup per item, 4 per compute unit};
- * the fastest of all is kept.  A trial is steps_per_trial steps (plus one
- * warm-up); h_best = {the most common member variant, zc, grid}, h_ms its
- * time per step.  The members advance by every trial step (re-initialise
- * afterwards for a clean start).  cache_path (or NULL): JSON-lines file; a
- * line with the same key (member shapes, dtype, device, variant count) and
- * its member variants is used without timing, a new result is appended.
+/* Pick the batch's tiles and cache blocking by timing: (1) every compiled
+ * variant for all members at 16- and 32-plane chunks, one workgroup per
+ * item, one set; (2) for each member the variant and z-chunk that step it
+ * alone fastest (each variant at the wave-count model's chunk for that
+ * lattice and at 4, 8, 16, 32 and 64 planes), then those tiles, and those
+ * variants at each member's model chunk or one chunk of {8, 16, 32, 48, 64}
+ * for all, x grid {one workgroup per item, 4 per compute unit}; (3) sets of
+ * at most 64, 128, 192 or 256 MiB, or one member per set, with the best so
+ * far and with the per-member tiles; the fastest of all is kept.  A trial
+ * is steps_per_trial steps (plus one warm-up) per set; h_best = {the most common member variant, zc
+ * (0 when the members' chunks differ), grid}, h_ms its time per step.  The
+ * members advance by every trial step (re-initialise afterwards for a clean
+ * start).  cache_path (or NULL): JSON-lines file; a line with the same key
+ * (member shapes, dtype, device, variant count) and its member variants,
+ * chunks and set budget is used without timing, a new result is appended.
  * Drops a captured graph. */
 scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
                               int32_t* h_best, double* h_ms);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libscdrop.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "scdrop.h")
 
 SCD_OK, SCD_EINVAL, SCD_EDEVICE, SCD_ENONFINITE, SCD_ENOINTERFACE, SCD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SCD_EDRIFT = -6
 SCD_F64, SCD_F32 = 0, 1
 SCD_WITH_ADJOINT = 1
 CA_FLAGS = {"NO_REF": 1, "E1_FLAT": 2, "E2_FLAT": 4, "RAY_LIMIT": 8, "NO_APEX": 16,
@@ -83,6 +84,8 @@ _PROTOS = {
     "scd_huang_angle": [ctypes.POINTER(ScdParams), _D, _D],
     "scd_surface_tension_z": [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "scd_observables": [_VP, ctypes.POINTER(ScdObs)],
+    "scd_set_mass_watchdog": [_VP, ctypes.c_double],
+    "scd_mass_drift": [_VP, ctypes.POINTER(ctypes.c_double)],
     "scd_contact_angle": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
     "scd_contact_angle_static": [_VP, ctypes.POINTER(ScdCaCfg), ctypes.POINTER(ScdCa)],
     "scd_ca_seed": [_VP, ctypes.POINTER(ScdCaCfg), _D, _VP],
@@ -91,6 +94,7 @@ _PROTOS = {
     "scd_adjoint_read": [_VP, ctypes.POINTER(_D)],
     "scd_ckpt_forward": [_VP, _VP, _VP, _I64, _I64, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
     "scd_ckpt_moment_cache": [_VP, _VP, _I64],
+    "scd_ckpt_seg_states": [_VP, _I64, ctypes.POINTER(_I64)],
     "scd_ckpt_backward": [_VP, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D, ctypes.POINTER(_D)],
     "scd_ckpt_backward2": [_VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.POINTER(ScdCaCfg), _D,
                            ctypes.POINTER(_D)],
@@ -108,6 +112,8 @@ _PROTOS = {
     "scd_batch_set_tile": [_VP, _I32, _I32, _I32],
     "scd_batch_set_member_tile": [_VP, _I32, _I32, _I32],
     "scd_batch_member_tile": [_VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
+    "scd_batch_set_blocking": [_VP, ctypes.c_int64],
+    "scd_batch_blocking": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_I32)],
     "scd_batch_step": [_VP, _I64],
     "scd_batch_graph_capture": [_VP, _I64],
     "scd_batch_graph_replay": [_VP, _I64],
@@ -380,13 +386,20 @@ class Lattice:
             check(st)
         return g.value, rs.value, list(prof), list(pphi)
 
-    def observables(self, raise_nonfinite=True):
+    def observables(self, raise_nonfinite=True, raise_drift=True):
         o = ScdObs()
         st = lib().scd_observables(self.h, ctypes.byref(o))
-        if st != SCD_ENONFINITE or raise_nonfinite:
+        if (st != SCD_ENONFINITE or raise_nonfinite) and (st != SCD_EDRIFT or raise_drift):
             check(st)
+        d = (ctypes.c_double * 2)()
+        check(lib().scd_mass_drift(self.h, d))
         return {"mass": (o.mass[0], o.mass[1]), "momentum": tuple(o.momentum), "finite": bool(o.finite),
-                "step": o.step, "status": st}
+                "step": o.step, "drift": (d[0], d[1]), "status": st}
+
+    def set_mass_watchdog(self, rel_tol):
+        """Flag (SCD_EDRIFT from observables) relative mass drift above
+        rel_tol since the state was last set; 0 only measures."""
+        check(lib().scd_set_mass_watchdog(self.h, float(rel_tol)))
 
     def contact_angle(self, cfg, static_scratch=False):
         """Both estimators of Sec. 3; static_scratch: through
@@ -542,11 +555,23 @@ class Batch:
             out.append((v.value, z.value))
         return out
 
+    def set_blocking(self, set_bytes):
+        """Step the members in sets of at most set_bytes of state, every step
+        of a call on one set before the next (0: one set of all members)."""
+        check(lib().scd_batch_set_blocking(self.h, int(set_bytes)))
+
+    def blocking(self):
+        """(set_bytes, number of sets)."""
+        sb, ns = ctypes.c_int64(), _I32()
+        check(lib().scd_batch_blocking(self.h, ctypes.byref(sb), ctypes.byref(ns)))
+        return sb.value, ns.value
+
     def step(self, n=1):
         check(lib().scd_batch_step(self.h, int(n)))
 
     def autotune(self, steps_per_trial=3, cache_path=None):
-        """Fastest (variant, zc, grid) and its ms per step; members advance."""
+        """Fastest (variant, zc, grid) and its ms per step (zc 0: each member
+        at its own chunk); members advance."""
         best = (_I32 * 3)()
         ms = _D()
         path = cache_path.encode() if cache_path else None

@@ -382,7 +382,14 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
 // Workgroups of the local pass (grid-stride over the nodes).  The FP64
 // kernel holds one wave per SIMD (its register set), so more workgroups
 // than two per CU only queue; the FP32 kernel fits several waves per SIMD.
-static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : ADJ_BLOCKS; }
+static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : 2048; }
+// The pass that gathers the transposed stencil (and with it the g_ab
+// gradient) runs one workgroup per 256 nodes up to ADJ_BLOCKS, each with its
+// own row of partials.
+static int adj_gather_grid(size_t N) {
+  const size_t g = (N + 255) / 256;
+  return (int)(g < (size_t)ADJ_BLOCKS ? g : (size_t)ADJ_BLOCKS);
+}
 
 template <typename real>
 static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
@@ -405,21 +412,20 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
                      lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   // FP64 adds the transposed stencil inside the push pass (one fewer sweep
   // of D); in FP32 the gathers slow that pass more than the sweep costs.
-  // The pass that gathers the stencil runs ADJ_BLOCKS workgroups, each with
-  // its row of g_ab partials.
+  // The pass that gathers the stencil has one row of g_ab partials per
+  // workgroup.
   constexpr bool FUSED = sizeof(real) == 8;
-  const int blocks = (int)((N + 255) / 256 > 8192 ? 8192 : (N + 255) / 256);
+  const int blocks = adj_gather_grid(N);
   if (!FUSED)
-    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(ADJ_BLOCKS), dim3(256), 0, s, links, rhof, nx,
-                       ny, nz, ph, qf, df, partials, accumulate);
-  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(FUSED ? ADJ_BLOCKS : blocks), dim3(256), 0,
-                     s, links, nx, ny, nz, ph, lam_in, rhof, qf, df, ef, lam_out, partials,
-                     accumulate);
+    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny,
+                       nz, ph, qf, df, partials, accumulate);
+  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(blocks), dim3(256), 0, s, links, nx, ny,
+                     nz, ph, lam_in, rhof, qf, df, ef, lam_out, partials, accumulate);
   return hipGetLastError();
 }
 
-__global__ void k_sum5(const double* __restrict__ partials, int nblocks, double* __restrict__ out,
-                       double* __restrict__ acc);
+__global__ void k_sum5(const double* __restrict__ partials, int nblocks, int ngather,
+                       double* __restrict__ out, double* __restrict__ acc);
 
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
@@ -443,24 +449,27 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
                          (float*)q_field, (float*)d_field, (float*)e_field, part, accumulate, s);
   if (e != hipSuccess) return e;
   if (accumulate) return hipSuccess;
-  return launch_adjoint_sum(dtype, partials, dparams_dev, s);
+  return launch_adjoint_sum(dtype, partials, (size_t)nx * ny * nz, dparams_dev, s);
 }
 
-hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s) {
+hipError_t launch_adjoint_sum(int dtype, const double* partials, size_t N, double* out,
+                              hipStream_t s) {
   hipLaunchKernelGGL(k_sum5, dim3(1), dim3(256), 0, s, partials, adj_local_grid(dtype == 0 ? 8 : 4),
-                     out, nullptr);
+                     adj_gather_grid(N), out, nullptr);
   return hipGetLastError();
 }
 
 // out = this step's parameter gradient; acc (if not NULL) += out, in step order
 __global__ __launch_bounds__(256) void k_sum5(const double* __restrict__ partials, int nblocks,
-                                              double* __restrict__ out, double* __restrict__ acc) {
+                                              int ngather, double* __restrict__ out,
+                                              double* __restrict__ acc) {
   __shared__ double sh[5 * 16];
   double v[5] = {0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
     for (int j = 0; j < 5; ++j) v[j] += partials[b * RED_STRIDE + j];
-  // the g_ab part gathered with the transposed stencil (ADJ_BLOCKS rows)
-  for (int b = threadIdx.x; b < ADJ_BLOCKS; b += blockDim.x) v[2] += partials[b * RED_STRIDE + GAB_COL];
+  // the g_ab part gathered with the transposed stencil (one row per
+  // workgroup of that pass)
+  for (int b = threadIdx.x; b < ngather; b += blockDim.x) v[2] += partials[b * RED_STRIDE + GAB_COL];
   block_sum_adj<5>(v, sh);
   if (threadIdx.x == 0)
     for (int j = 0; j < 5; ++j) {

@@ -145,6 +145,12 @@ struct scd_lattice {
   int64_t ckpt_base;  // step at which the last checkpointed forward began
   void* mom_cache = nullptr;      // caller buffer of moment fields of recomputed steps
   int64_t mom_cache_steps = 0;    // ... and how many steps (8 x N reals each) it holds
+  // mass-drift watchdog: tolerance (0: off), reference masses (taken by the
+  // first scd_observables after the state was set) and the last drift
+  double watch_tol = 0.0;
+  bool mass_ref_ok = false;
+  double mass_ref[2] = {0.0, 0.0};
+  double drift[2] = {0.0, 0.0};
   uint32_t* links() const { return (uint32_t*)(work + wl.links); }
   double* wd(size_t off) const { return (double*)(work + off); }
   void* wv(size_t off) const { return (void*)(work + off); }
@@ -349,6 +355,7 @@ scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const dou
   HIPCHK(launch_init(h->p.dtype, h->pop[h->cur], d_rho_a, d_rho_b, h->links(), h->p.nx, h->p.ny,
                      h->p.nz, h->stream));
   h->step = 0;
+  h->mass_ref_ok = false;
   return SCD_OK;
 }
 
@@ -372,6 +379,7 @@ scd_status scd_set_state(scd_lattice* h, const void* d_src, int64_t step) {
   HIPCHK(hipMemcpyAsync(h->pop[h->cur], d_src, pop_elems(&h->p) * real_size(h->p.dtype),
                         hipMemcpyDeviceToDevice, h->stream));
   h->step = step;
+  h->mass_ref_ok = false;
   return SCD_OK;
 }
 
@@ -399,6 +407,7 @@ scd_status scd_pop_unpack(const scd_lattice* h, const void* d_blocked, void* d_p
 scd_status scd_fill_state(scd_lattice* h, double value) {
   if (!h) return fail(SCD_EINVAL, "NULL handle");
   HIPCHK(launch_fill(h->p.dtype, h->pop[h->cur], pop_elems(&h->p), value, h->stream));
+  h->mass_ref_ok = false;
   return SCD_OK;
 }
 
@@ -520,6 +529,32 @@ scd_status scd_observables(scd_lattice* h, scd_obs* out) {
   out->pad = 0;
   out->step = h->step;
   if (!out->finite) return fail(SCD_ENONFINITE, "%.0f non-finite populations", r[5]);
+  // the watchdog: relative change of each species' mass since the reference
+  if (!h->mass_ref_ok) {
+    h->mass_ref[0] = r[0];
+    h->mass_ref[1] = r[1];
+    h->mass_ref_ok = true;
+  }
+  for (int a = 0; a < 2; ++a)
+    h->drift[a] = h->mass_ref[a] != 0.0 ? (r[a] - h->mass_ref[a]) / h->mass_ref[a] : r[a];
+  const double worst = std::max(std::fabs(h->drift[0]), std::fabs(h->drift[1]));
+  if (h->watch_tol > 0.0 && worst > h->watch_tol)
+    return fail(SCD_EDRIFT, "mass drift %.3e exceeds the watchdog tolerance %.3e at step %lld", worst,
+                h->watch_tol, (long long)h->step);
+  return SCD_OK;
+}
+
+scd_status scd_set_mass_watchdog(scd_lattice* h, double rel_tol) {
+  if (!h) return fail(SCD_EINVAL, "NULL handle");
+  if (!(rel_tol >= 0.0)) return fail(SCD_EINVAL, "watchdog tolerance must be >= 0");
+  h->watch_tol = rel_tol;
+  return SCD_OK;
+}
+
+scd_status scd_mass_drift(const scd_lattice* h, double* h_drift) {
+  if (!h || !h_drift) return fail(SCD_EINVAL, "NULL argument");
+  h_drift[0] = h->drift[0];
+  h_drift[1] = h->drift[1];
   return SCD_OK;
 }
 
@@ -598,7 +633,7 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc) {
   if (!h || !h_acc) return fail(SCD_EINVAL, "NULL argument");
   if (!(h->p.flags & SCD_WITH_ADJOINT))
     return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
-  HIPCHK(launch_adjoint_sum(h->p.dtype, h->wd(h->wl.adj_acc), h->wd(h->wl.adj_dparams) + 8,
+  HIPCHK(launch_adjoint_sum(h->p.dtype, h->wd(h->wl.adj_acc), h->N, h->wd(h->wl.adj_dparams) + 8,
                             h->stream));
   HIPCHK(hipMemcpyAsync(h_acc, h->wd(h->wl.adj_dparams) + 8, 5 * sizeof(double),
                         hipMemcpyDeviceToHost, h->stream));
@@ -665,7 +700,12 @@ scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double*
 // momenta of the post-stream populations of the state it reads, and the
 // adjoint of that state reads them instead of pulling its populations to
 // form them; for the last state of the segment, which no recomputed step
-// reads, the adjoint forms them itself.
+// reads, the adjoint forms them itself.  The adjoint of a state whose
+// moments are cached reads nothing else of the state, so with the cache the
+// recomputed states only alternate between two slots of d_seg (state
+// t0 + 1 + j in slot j mod 2): a segment then needs two states of room
+// instead of t1 - t0 - 1, and long segments fit where their states would
+// not.
 static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const void* d_start,
                                   void* d_seg, void* lam[2], int* lc) {
   const size_t bytes = pop_elems(&h->p) * real_size(h->p.dtype);
@@ -673,20 +713,30 @@ static scd_status reverse_segment(scd_lattice* h, int64_t t0, int64_t t1, const 
   const bool cache = h->mom_cache && h->mom_cache_steps >= t1 - t0 - 1 &&
                      variant_writes_moments(h->variant);
   auto state = [&](int64_t t) -> const void* {
-    return t == t0 ? d_start : (const char*)d_seg + (size_t)(t - t0 - 1) * bytes;
+    if (t == t0) return d_start;
+    const int64_t j = t - t0 - 1;
+    return (const char*)d_seg + (size_t)(cache ? (j & 1) : j) * bytes;
   };
   auto mom = [&](int64_t t) -> void* {
     return cache && t + 1 < t1 ? (char*)h->mom_cache + (size_t)(t - t0) * mbytes : nullptr;
   };
   for (int64_t t = t0; t + 1 < t1; ++t)
-    HIPCHK(launch_step(h->p.dtype, state(t), (char*)d_seg + (size_t)(t - t0) * bytes, h->links(),
-                       h->p.nx, h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream,
-                       mom(t)));
+    HIPCHK(launch_step(h->p.dtype, state(t), const_cast<void*>(state(t + 1)), h->links(), h->p.nx,
+                       h->p.ny, h->p.nz, h->ph, h->variant, h->zc, h->remap, h->stream, mom(t)));
   for (int64_t t = t1 - 1; t >= t0; --t) {
     scd_status st = adjoint_enqueue(h, state(t), lam[*lc], lam[1 - *lc], true, mom(t));
     if (st) return st;
     *lc = 1 - *lc;
   }
+  return SCD_OK;
+}
+
+scd_status scd_ckpt_seg_states(const scd_lattice* h, int64_t seg_len, int64_t* h_states) {
+  if (!h || !h_states) return fail(SCD_EINVAL, "NULL argument");
+  if (seg_len < 1) return fail(SCD_EINVAL, "segment length must be >= 1");
+  const bool cache = h->mom_cache && h->mom_cache_steps >= seg_len - 1 &&
+                     variant_writes_moments(h->variant);
+  *h_states = cache ? std::min<int64_t>(2, seg_len - 1) : seg_len - 1;
   return SCD_OK;
 }
 
@@ -979,14 +1029,17 @@ struct scd_batch {
   int dtype;
   std::vector<scd_lattice*> views;
   char* arena;
-  size_t desc_off[2];  // descriptor tables for even and odd parity
-  size_t items_off;
+  std::vector<char> desc[2];  // host descriptors of every member, even and odd parity
   int nitems;
   int variant, zc, grid;  // the last uniform setting (scd_batch_set_tile)
   int remap;              // XCD-contiguous ranges of the work list
   std::vector<int> mvar, mzc;  // per member: step variant and z-chunk
+  int64_t set_bytes;           // cache-blocking budget (0: one set)
+  int nsets;
   struct Group {
-    int variant, start, count;  // a run of items that share one variant
+    int set, variant, count;   // members of one set and variant: one launch per step
+    std::vector<int> members;  // at most BATCH_DESC_MAX
+    std::vector<int> geo;      // per member: tile columns along x, chunks per column, chunk length
   };
   std::vector<Group> groups;
   hipStream_t stream;
@@ -1001,18 +1054,12 @@ namespace {
 
 struct BatchLayout {
   std::vector<size_t> pop0, pop1, work;
-  size_t desc[2], items, total;
-  int nitems;
+  size_t total;
 };
-
-int batch_items_of(const scd_params& p, int tx, int ty, int zc) {
-  return ((p.nx + tx - 1) / tx) * ((p.ny + ty - 1) / ty) * ((p.nz + zc - 1) / zc);
-}
 
 BatchLayout batch_layout(int n, const scd_params* p) {
   BatchLayout L;
   size_t off = 0;
-  L.nitems = 0;
   for (int i = 0; i < n; ++i) {
     size_t pb, wb;
     scd_sizes(&p[i], &pb, &wb);
@@ -1020,36 +1067,49 @@ BatchLayout batch_layout(int n, const scd_params* p) {
     L.pop1.push_back(off); off += align256(pb);
     L.work.push_back(off); off += align256(wb);
   }
-  const size_t ds = latdev_size(p[0].dtype);
-  L.desc[0] = off; off += align256(ds * n);
-  L.desc[1] = off; off += align256(ds * n);
-  // room for the largest item list: every member with the compiled tile
-  // shape that cuts it into the most items, at one plane per chunk
-  int maxitems = 0;
-  for (int i = 0; i < n; ++i) {
-    int m = 0;
-    for (int t = 0; t < variant_count(); ++t) {
-      int a, b, v, w;
-      variant_at(t, &a, &b, &v, &w);
-      m = std::max(m, batch_items_of(p[i], a, b, 1));
-    }
-    maxitems += m;
-  }
-  L.items = off; off += align256((size_t)maxitems * 16);
   L.total = off;
   return L;
 }
 
+// Bytes a member's step streams through: both population buffers and the
+// link masks.
+size_t member_state_bytes(const scd_lattice* v) {
+  size_t pb = 0;
+  (void)scd_sizes(&v->p, &pb, nullptr);
+  return 2 * pb + v->N * sizeof(uint32_t);
+}
+
 scd_status batch_upload(scd_batch* b) {
-  // descriptors for both parities and the (lattice, tile) work list; the
-  // members are taken in order of their step variant, so that the items of
-  // one variant form one contiguous group (one launch per group and step)
+  // descriptors for both parities and the launch groups.  The members are
+  // packed, in index order, into sets of at most set_bytes of state; within
+  // a set they are taken in order of their step variant, and the members of
+  // one set and variant form launch groups of at most BATCH_DESC_MAX (one
+  // launch per group and step).  A member's items, (tile column, z-chunk)
+  // pairs, are numbered as in the single-lattice step.
   const size_t ds = latdev_size(b->dtype);
-  std::vector<char> d0(ds * b->n), d1(ds * b->n);
-  std::vector<int32_t> items;
-  std::vector<int> order(b->n);
+  std::vector<char>& d0 = b->desc[0];
+  std::vector<char>& d1 = b->desc[1];
+  d0.assign(ds * b->n, 0);
+  d1.assign(ds * b->n, 0);
+  std::vector<int> order(b->n), mset(b->n);
+  {
+    int s = 0;
+    size_t acc = 0;
+    for (int i = 0; i < b->n; ++i) {
+      const size_t fb = member_state_bytes(b->views[i]);
+      if (b->set_bytes > 0 && acc > 0 && acc + fb > (size_t)b->set_bytes) {
+        ++s;
+        acc = 0;
+      }
+      mset[i] = s;
+      acc += fb;
+    }
+    b->nsets = s + 1;
+  }
   for (int i = 0; i < b->n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->mvar[x] < b->mvar[y]; });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return mset[x] != mset[y] ? mset[x] < mset[y] : b->mvar[x] < b->mvar[y];
+  });
   b->groups.clear();
   for (int i = 0; i < b->n; ++i) {
     scd_lattice* v = b->views[i];
@@ -1058,39 +1118,26 @@ scd_status batch_upload(scd_batch* b) {
     latdev_fill(b->dtype, d1.data() + ds * i, v->pop[1], v->pop[0], v->links(), v->p.nx, v->p.ny,
                 v->p.nz, v->ph);
   }
+  int64_t total = 0;
   for (int i : order) {
     scd_lattice* v = b->views[i];
     const int zc = std::min(b->mzc[i], v->p.nz);
-    if (zc > 32767) return fail(SCD_EINVAL, "z-chunk %d exceeds 32767 planes", zc);
     int tx, ty, var, wpe;
     variant_at(b->mvar[i], &tx, &ty, &var, &wpe);
     const int gx = (v->p.nx + tx - 1) / tx, gy = (v->p.ny + ty - 1) / ty;
     const int gz = (v->p.nz + zc - 1) / zc;
-    const int start = (int)(items.size() / 4);
-    if (b->groups.empty() || b->groups.back().variant != b->mvar[i])
-      b->groups.push_back({b->mvar[i], start, 0});
-    // chunks of a column adjacent, then the columns along x, then y; even
-    // chunks march down and odd ones up, so that two neighbouring chunks
-    // reach their shared boundary planes together (as in the single-lattice
-    // step)
-    for (int by = 0; by < gy; ++by)
-      for (int bx = 0; bx < gx; ++bx)
-        for (int bz = 0; bz < gz; ++bz) {
-          const int za = bz * zc, zlen = std::min(zc, v->p.nz - za);
-          const bool down = !(bz & 1) && gz > 1;
-          items.push_back(i);
-          items.push_back(bx);
-          items.push_back(by);
-          items.push_back((int32_t)((uint32_t)za | ((uint32_t)zlen << 16) | (down ? 0x80000000u : 0u)));
-        }
-    b->groups.back().count += (int)(items.size() / 4) - start;
+    if (b->groups.empty() || b->groups.back().variant != b->mvar[i] || b->groups.back().set != mset[i] ||
+        (int)b->groups.back().members.size() == BATCH_DESC_MAX)
+      b->groups.push_back({mset[i], b->mvar[i], 0, {}, {}});
+    scd_batch::Group& g = b->groups.back();
+    const int64_t items = (int64_t)gx * gy * gz;
+    if (g.count + items > INT32_MAX / 2) return fail(SCD_EINVAL, "too many tiles in one launch group");
+    g.members.push_back(i);
+    g.geo.insert(g.geo.end(), {gx, gz, zc});
+    g.count += (int)items;
+    total += items;
   }
-  b->nitems = (int)(items.size() / 4);
-  HIPCHK(hipMemcpyAsync(b->arena + b->desc_off[0], d0.data(), d0.size(), hipMemcpyHostToDevice, b->stream));
-  HIPCHK(hipMemcpyAsync(b->arena + b->desc_off[1], d1.data(), d1.size(), hipMemcpyHostToDevice, b->stream));
-  HIPCHK(hipMemcpyAsync(b->arena + b->items_off, items.data(), items.size() * 4, hipMemcpyHostToDevice,
-                        b->stream));
-  HIPCHK(hipStreamSynchronize(b->stream));
+  b->nitems = (int)std::min<int64_t>(total, INT32_MAX);
   return SCD_OK;
 }
 
@@ -1114,23 +1161,46 @@ void batch_drop_graph(scd_batch* b) {
 }
 
 scd_status batch_enqueue(scd_batch* b, int64_t nsteps) {
-  for (int64_t s = 0; s < nsteps; ++s) {
-    // one launch per variant group: one workgroup per item, or a persistent
-    // grid (a multiple of 8 with the XCD remap, so that each block stays on
-    // one XCD's range)
-    for (const auto& g : b->groups) {
-      const int slots = b->remap ? 8 * ((g.count + 7) / 8) : g.count;
-      int grid = (b->grid <= 0 || b->grid > slots) ? slots : b->grid;
-      if (b->remap) grid = 8 * ((grid + 7) / 8);
-      HIPCHK(launch_step_batch(b->dtype, b->arena + b->desc_off[b->parity],
-                               b->arena + b->items_off + (size_t)g.start * 16, g.count, grid,
-                               g.variant, b->remap, b->stream));
+  // set by set, every step of the call: the members of one set are stepped
+  // nsteps times before the next set starts (members are independent, so
+  // the order changes no result).  Per step, one launch per variant group:
+  // one workgroup per item, or a persistent grid (a multiple of 8 with the
+  // XCD remap, so that each block stays on one XCD's range)
+  size_t g0 = 0;
+  while (g0 < b->groups.size()) {
+    size_t g1 = g0;
+    while (g1 < b->groups.size() && b->groups[g1].set == b->groups[g0].set) ++g1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      const int par = b->parity ^ (int)(s & 1);
+      for (size_t gi = g0; gi < g1; ++gi) {
+        const auto& g = b->groups[gi];
+        if (g.members.size() == 1 && b->grid <= 0) {
+          // a group of one lattice, one workgroup per item, is the
+          // single-lattice launch: the same kernel scd_step runs
+          scd_lattice* v = b->views[g.members[0]];
+          HIPCHK(launch_step(b->dtype, v->pop[par], v->pop[1 - par], v->links(), v->p.nx, v->p.ny,
+                             v->p.nz, v->ph, g.variant, g.geo[2], b->remap, b->stream));
+          continue;
+        }
+        const int slots = b->remap ? 8 * ((g.count + 7) / 8) : g.count;
+        int grid = (b->grid <= 0 || b->grid > slots) ? slots : b->grid;
+        if (b->remap) grid = 8 * ((grid + 7) / 8);
+        // the group's descriptors for this parity, passed by value
+        char descs[BATCH_DESC_MAX * 256];
+        const size_t ds = latdev_size(b->dtype);
+        if (ds > 256) return fail(SCD_EINVAL, "lattice descriptor larger than expected");
+        for (size_t m = 0; m < g.members.size(); ++m)
+          memcpy(descs + m * ds, b->desc[par].data() + (size_t)g.members[m] * ds, ds);
+        HIPCHK(launch_step_batch(b->dtype, descs, (int)g.members.size(), g.geo.data(), grid,
+                                 g.variant, b->remap, b->stream));
+      }
     }
-    b->parity ^= 1;
-    for (scd_lattice* v : b->views) {
-      v->cur = b->parity;
-      v->step += 1;
-    }
+    g0 = g1;
+  }
+  b->parity ^= (int)(nsteps & 1);
+  for (scd_lattice* v : b->views) {
+    v->cur = b->parity;
+    v->step += nsteps;
   }
   return SCD_OK;
 }
@@ -1162,11 +1232,10 @@ scd_status scd_batch_create(int32_t n, const scd_params* p, const uint8_t* const
   b->n = n;
   b->dtype = p[0].dtype;
   b->arena = (char*)d_arena;
-  b->desc_off[0] = L.desc[0];
-  b->desc_off[1] = L.desc[1];
-  b->items_off = L.items;
   batch_default_tile(p[0].dtype, &b->variant, &b->zc, &b->grid);
   b->remap = 1;
+  b->set_bytes = 0;
+  b->nsets = 1;
   b->mvar.assign(n, b->variant);
   b->mzc.assign(n, b->zc);
   b->stream = (hipStream_t)stream;
@@ -1284,26 +1353,30 @@ scd_status scd_batch_graph_capture(scd_batch* b, int64_t nsteps) {
   return SCD_OK;
 }
 
-// Per-member variants of a cached batch tuning: the "members" list of the
-// last line whose key matches (empty when there is none).
-static std::vector<int> cache_members(const char* path, const std::string& key) {
-  std::vector<int> out;
+// A named integer list (or, with one element, a number) of the last line
+// of a cached batch tuning whose key matches (empty when there is none).
+static std::vector<long long> cache_list(const char* path, const std::string& key, const char* name) {
+  std::vector<long long> out;
   if (!path) return out;
   std::ifstream f(path);
   std::string line;
   const std::string k = "\"key\": \"" + key + "\"";
+  const std::string field = std::string("\"") + name + "\": ";
   while (std::getline(f, line)) {
     if (line.find(k) == std::string::npos) continue;
-    const char* m = strstr(line.c_str(), "\"members\": [");
-    if (!m) continue;
-    std::vector<int> v;
-    const char* c = m + strlen("\"members\": [");
+    const size_t at = line.find(field);
+    if (at == std::string::npos) continue;
+    std::vector<long long> v;
+    const char* c = line.c_str() + at + field.size();
+    const bool list = *c == '[';
+    if (list) ++c;
     while (*c && *c != ']') {
       char* e = nullptr;
-      const long x = strtol(c, &e, 10);
+      const long long x = strtoll(c, &e, 10);
       if (e == c) break;
-      v.push_back((int)x);
+      v.push_back(x);
       c = e;
+      if (!list) break;
       while (*c == ',' || *c == ' ') ++c;
     }
     out = v;
@@ -1321,30 +1394,61 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
     for (int d : {v->p.nx, v->p.ny, v->p.nz}) hsh = (hsh ^ (uint64_t)d) * 1099511628211ull;
   std::ostringstream ko;
   ko << "batch" << b->n << ":" << std::hex << hsh << std::dec << ":" << (b->dtype == SCD_F64 ? "f64" : "f32")
-     << ":" << device_name() << ":v" << variant_count() << ":members";
+     << ":" << device_name() << ":v" << variant_count() << ":sets";
   const std::string key = ko.str();
-  int cached[3];
-  double cms;
-  if (cache_lookup3(cache_path, key, cached, &cms) && cached[0] >= 0 && cached[0] < variant_count()) {
-    const std::vector<int> mv = cache_members(cache_path, key);
-    if ((int)mv.size() == b->n) {
-      for (int v : mv)
-        if (v < 0 || v >= variant_count()) return fail(SCD_EINVAL, "bad cached variant %d", v);
-      b->mvar = mv;
-      b->mzc.assign(b->n, cached[1]);
-      b->variant = cached[0];
-      b->zc = cached[1];
-      b->grid = cached[2];
-      for (int i = 0; i < b->n; ++i) {
-        b->views[i]->variant = mv[i];
-        b->views[i]->zc = std::min(cached[1], b->views[i]->p.nz);
+
+  // members' variants and chunks (zc 0: each member's model chunk), grid and
+  // set budget, applied and uploaded
+  auto apply = [&](const std::vector<int>& mv, const std::vector<int>& mz, int grid,
+                   int64_t sb) -> scd_status {
+    b->mvar = mv;
+    b->mzc = mz;
+    b->grid = grid;
+    b->set_bytes = sb;
+    for (int i = 0; i < b->n; ++i) {
+      b->views[i]->variant = mv[i];
+      b->views[i]->zc = std::min(mz[i], b->views[i]->p.nz);
+    }
+    batch_drop_graph(b);
+    return batch_upload(b);
+  };
+  auto chunks = [&](const std::vector<int>& mv, int zc) {
+    std::vector<int> mz(b->n);
+    for (int i = 0; i < b->n; ++i) mz[i] = zc > 0 ? zc : default_zc(b->views[i]->p, mv[i]);
+    return mz;
+  };
+  auto summary = [&](const std::vector<int>& mv, const std::vector<int>& mz) {
+    int cnt[64] = {0}, top = mv[0];
+    for (int x : mv)
+      if (x < 64 && ++cnt[x] > cnt[top]) top = x;
+    bool same = true;
+    for (int z : mz) same = same && z == mz[0];
+    b->variant = top;
+    b->zc = same ? mz[0] : 0;
+  };
+
+  {
+    int cached[3];
+    double cms;
+    if (cache_lookup3(cache_path, key, cached, &cms) && cached[0] >= 0 && cached[0] < variant_count()) {
+      const std::vector<long long> mv = cache_list(cache_path, key, "members");
+      const std::vector<long long> mz = cache_list(cache_path, key, "zcs");
+      const std::vector<long long> sb = cache_list(cache_path, key, "set_bytes");
+      if ((int)mv.size() == b->n && (int)mz.size() == b->n && sb.size() == 1 && sb[0] >= 0) {
+        std::vector<int> v(b->n), z(b->n);
+        for (int i = 0; i < b->n; ++i) {
+          if (mv[i] < 0 || mv[i] >= variant_count()) return fail(SCD_EINVAL, "bad cached variant %lld", mv[i]);
+          if (mz[i] < 1 || mz[i] > 32767) return fail(SCD_EINVAL, "bad cached z-chunk %lld", mz[i]);
+          v[i] = (int)mv[i];
+          z[i] = (int)mz[i];
+        }
+        scd_status st = apply(v, z, cached[2], sb[0]);
+        if (st) return st;
+        summary(v, z);
+        for (int j = 0; j < 3; ++j) best[j] = cached[j];
+        *best_ms = cms;
+        return SCD_OK;
       }
-      batch_drop_graph(b);
-      scd_status st = batch_upload(b);
-      if (st) return st;
-      for (int j = 0; j < 3; ++j) best[j] = cached[j];
-      *best_ms = cms;
-      return SCD_OK;
     }
   }
   const int cus = device_cus();
@@ -1364,99 +1468,128 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
     *per = ms / steps_per_trial;
     return SCD_OK;
   };
-  // (1) one variant for all members: every compiled variant at 16- and
-  // 32-plane chunks, one workgroup per item
   double bms = 1e30;
-  int bb[3] = {b->variant, b->zc, b->grid};
-  std::vector<int> bmem(b->n, b->variant);
+  std::vector<int> bmem(b->n, b->variant), bzc(b->n, b->zc);
+  int bgrid = 0;
+  int64_t bsb = 0;
+  auto trial = [&](const std::vector<int>& mv, const std::vector<int>& mz, int grid,
+                   int64_t sb) -> scd_status {
+    scd_status st = apply(mv, mz, grid, sb);
+    if (st) return st;
+    double per;
+    st = time_batch(&per);
+    if (st) return st;
+    if (per < bms) {
+      bms = per;
+      bmem = mv;
+      bzc = mz;
+      bgrid = grid;
+      bsb = sb;
+    }
+    return SCD_OK;
+  };
+  // (1) one variant for all members, all members in one set: every compiled
+  // variant at 16- and 32-plane chunks, one workgroup per item
   for (int i = 0; i < variant_count(); ++i)
     for (int zc : {16, 32}) {
-      scd_status st = scd_batch_set_tile(b, i, zc, 0);
+      const std::vector<int> mv(b->n, i);
+      scd_status st = trial(mv, chunks(mv, zc), 0, 0);
       if (st) return st;
-      double per;
-      st = time_batch(&per);
-      if (st) return st;
-      if (per < bms) {
-        bms = per;
-        bb[0] = i; bb[1] = zc; bb[2] = 0;
-        bmem.assign(b->n, i);
-      }
     }
-  // (2) a variant per member: the fastest on the member stepped alone (each
-  // variant at the z-chunk the wave-count model gives it for that lattice,
-  // over an even number of steps, so that the member keeps the batch's buffer
-  // parity), then the batch-wide chunk and grid for those variants
-  const int trial = 2 * ((steps_per_trial + 1) / 2);
-  std::vector<int> mv(b->n);
+  // (2) a tile per member: the fastest variant and z-chunk on the member
+  // stepped alone (each variant at the wave-count model's chunk for that
+  // lattice and at 4, 8, 16, 32 and 64 planes, over an even number of steps,
+  // so that the member keeps the batch's buffer parity); then those tiles,
+  // and those variants at one chunk for all, in one set, with both grids
+  const int even = 2 * ((steps_per_trial + 1) / 2);
+  std::vector<int> mv(b->n), mz(b->n);
   for (int m = 0; m < b->n; ++m) {
     scd_lattice* v = b->views[m];
     double best_t = 1e30;
-    mv[m] = bb[0];
+    mv[m] = bmem[m];
+    mz[m] = std::min(bzc[m], v->p.nz);
     for (int i = 0; i < variant_count(); ++i) {
       int tx, ty, var, wpe;
       variant_at(i, &tx, &ty, &var, &wpe);
       if (tx > 2 * v->p.nx && tx > 16) continue;  // mostly idle lanes
-      v->variant = i;
-      v->zc = default_zc(v->p, i);
-      scd_status st = enqueue_steps(v, 2);
-      if (st) return st;
-      HIPCHK(hipEventRecord(e0, b->stream));
-      st = enqueue_steps(v, trial);
-      if (st) return st;
-      HIPCHK(hipEventRecord(e1, b->stream));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_t) {
-        best_t = ms;
-        mv[m] = i;
+      const int model = default_zc(v->p, i);
+      for (int zc : {model, 4, 8, 16, 32, 64}) {
+        const int z = std::min(zc, v->p.nz);
+        if (zc != model && z == std::min(model, v->p.nz)) continue;  // timed already
+        v->variant = i;
+        v->zc = z;
+        scd_status st = enqueue_steps(v, 2);
+        if (st) return st;
+        HIPCHK(hipEventRecord(e0, b->stream));
+        st = enqueue_steps(v, even);
+        if (st) return st;
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_t) {
+          best_t = ms;
+          mv[m] = i;
+          mz[m] = z;
+        }
       }
     }
   }
-  for (int zc : {8, 16, 32, 48, 64})
-    for (int grid : {0, 4 * cus}) {
-      b->mvar = mv;
-      b->mzc.assign(b->n, zc);
-      b->grid = grid;
-      batch_drop_graph(b);
-      scd_status st = batch_upload(b);
+  for (int grid : {0, 4 * cus}) {
+    scd_status st = trial(mv, mz, grid, 0);
+    if (st) return st;
+    for (int zc : {0, 8, 16, 32, 48, 64}) {
+      st = trial(mv, chunks(mv, zc), grid, 0);
       if (st) return st;
-      double per;
-      st = time_batch(&per);
-      if (st) return st;
-      if (per < bms) {
-        bms = per;
-        int cnt[64] = {0}, top = mv[0];
-        for (int x : mv)
-          if (x < 64 && ++cnt[x] > cnt[top]) top = x;
-        bb[0] = top; bb[1] = zc; bb[2] = grid;
-        bmem = mv;
-      }
     }
+  }
+  // (3) cache blocking: sets of at most 64, 128, 192 or 256 MiB of state, or
+  // every member alone, with the best so far and with the per-member tiles
+  {
+    const std::vector<int> m0 = bmem, z0 = bzc;
+    const int g0 = bgrid;
+    for (int64_t mib : {64, 128, 192, 256, 0}) {
+      const int64_t sb = mib ? mib << 20 : 1;
+      scd_status st = trial(m0, z0, g0, sb);
+      if (st) return st;
+      st = trial(mv, mz, 0, sb);
+      if (st) return st;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // apply the fastest
-  b->mvar = bmem;
-  b->mzc.assign(b->n, bb[1]);
-  b->variant = bb[0];
-  b->zc = bb[1];
-  b->grid = bb[2];
-  for (int i = 0; i < b->n; ++i) {
-    b->views[i]->variant = bmem[i];
-    b->views[i]->zc = std::min(bb[1], b->views[i]->p.nz);
-  }
-  batch_drop_graph(b);
-  scd_status st = batch_upload(b);
+  scd_status st = apply(bmem, bzc, bgrid, bsb);
   if (st) return st;
-  for (int j = 0; j < 3; ++j) best[j] = bb[j];
+  summary(bmem, bzc);
+  best[0] = b->variant;
+  best[1] = b->zc;
+  best[2] = bgrid;
   *best_ms = bms;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    f << "{\"key\": \"" << key << "\", \"best\": [" << bb[0] << ", " << bb[1] << ", " << bb[2]
+    f << "{\"key\": \"" << key << "\", \"best\": [" << best[0] << ", " << best[1] << ", " << best[2]
       << "], \"members\": [";
     for (int i = 0; i < b->n; ++i) f << (i ? ", " : "") << bmem[i];
-    f << "], \"ms\": " << std::setprecision(17) << bms << "}\n";
+    f << "], \"zcs\": [";
+    for (int i = 0; i < b->n; ++i) f << (i ? ", " : "") << bzc[i];
+    f << "], \"set_bytes\": " << bsb << ", \"ms\": " << std::setprecision(17) << bms << "}\n";
   }
+  return SCD_OK;
+}
+
+scd_status scd_batch_set_blocking(scd_batch* b, int64_t set_bytes) {
+  if (!b) return fail(SCD_EINVAL, "NULL handle");
+  if (set_bytes < 0) return fail(SCD_EINVAL, "set_bytes < 0");
+  b->set_bytes = set_bytes;
+  batch_drop_graph(b);
+  return batch_upload(b);
+}
+
+scd_status scd_batch_blocking(const scd_batch* b, int64_t* set_bytes, int32_t* nsets) {
+  if (!b || !set_bytes || !nsets) return fail(SCD_EINVAL, "NULL argument");
+  *set_bytes = b->set_bytes;
+  *nsets = b->nsets;
   return SCD_OK;
 }
 

@@ -48,9 +48,12 @@ hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* li
                        int ny, int nz, const PhysD& ph, int variant, int zc, int remap,
                        hipStream_t s, void* mom_out = nullptr);
 bool variant_writes_moments(int variant);
-// items: int4 {lattice, bx, by, zw} (zw: first plane | chunk length << 16
-// | downward << 31); grid workgroups walk them (remap: XCD-contiguous ranges)
-hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
+// h_descs: ndesc (<= BATCH_DESC_MAX) lattice descriptors of latdev_size bytes
+// each, and h_geo: per descriptor {tile columns along x, z-chunks per column,
+// chunk length}, both on the host (passed by value); grid workgroups walk
+// the members' (column, chunk) items (remap: XCD-contiguous ranges)
+constexpr int BATCH_DESC_MAX = 16;
+hipError_t launch_step_batch(int dtype, const void* h_descs, int ndesc, const int* h_geo, int grid,
                              int variant, int remap, hipStream_t s);
 size_t latdev_size(int dtype);
 void latdev_fill(int dtype, void* out, const void* src, void* dst, const uint32_t* links, int nx,
@@ -94,7 +97,7 @@ hipError_t launch_ca_seed(int dtype, const uint32_t* links, int nx, int ny, int 
                           void* lambda, hipStream_t s);
 
 // adjoint.hip
-constexpr int ADJ_BLOCKS = 2048;
+constexpr int ADJ_BLOCKS = 8192;  // rows of adjoint partials (workgroups of the gathering pass, at most)
 // One reverse step.  mom_cached (or nullptr): the moments of the post-stream
 // populations of state_t in the layout of launch_step's mom_out, written
 // earlier by the step that read state_t; the local pass then takes rho and j
@@ -108,7 +111,7 @@ hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, vo
                           void* rho_field, void* j_field, const void* mom_cached, void* q_field,
                           void* d_field, void* e_field, double* partials, double* dparams_dev,
                           double* acc_partials, hipStream_t s);
-hipError_t launch_adjoint_sum(int dtype, const double* partials, double* out, hipStream_t s);
+hipError_t launch_adjoint_sum(int dtype, const double* partials, size_t N, double* out, hipStream_t s);
 hipError_t launch_zero(double* p, int n, hipStream_t s);
 
 }  // namespace scd

@@ -17,6 +17,8 @@
 //     coalesced stores.  The pulled populations of p - 1 stay in registers.
 // HBM traffic per fluid node and step is one read and one write of each
 // population (plus a 4-byte link mask); everything else is on chip.
+#include <cstring>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -1100,32 +1102,49 @@ void k_step(LatDev<real> L, int gx, int gy, int nchunks, int zc, int remap) {
   run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds, (bz & 1) || nchunks == 1 ? 1 : -1);
 }
 
-// Batched: the grid walks a list of (lattice, tile) items, one item per
-// workgroup at a time (a persistent grid when it is shorter than the list).
-// Item {lattice, bx, by, zw}: zw holds the first plane in bits 0-15, the
-// chunk length in bits 16-30 and the march direction in bit 31 (set: down).
-// With remap, slot s of the walk takes item (s mod 8) * per + s / 8, so that
-// each XCD (blocks are dealt to the 8 XCDs round-robin, and a persistent
-// grid is a multiple of 8) works through one contiguous range of the list,
-// in which the chunks of a column and the columns of a lattice are adjacent.
+// Batched: the grid walks the (member, tile) items of up to BATCH_DESC_MAX
+// lattices, one item per workgroup at a time (a persistent grid when it is
+// shorter than the list).  Member m owns items start[m] .. start[m + 1] - 1,
+// its gx * gy tile columns cut into gz chunks of zc planes, in the order of
+// the single-lattice step (chunks of a column adjacent, then x, then y), and
+// even chunks march down, odd ones up, as there.  The descriptors and this
+// table travel by value in the kernel arguments, like the single-lattice
+// step's: read from the argument segment, the descriptors' pointers are
+// known to address global memory (so the tile's loads and stores take the
+// global scalar-base + vector-offset forms; read from a table in device
+// memory they would be flat accesses), and a workgroup finds its tile with
+// no memory access before its first pull.  With remap, slot s of the walk
+// takes item (s mod 8) * per + s / 8, so that each XCD (blocks are dealt to
+// the 8 XCDs round-robin, and a persistent grid is a multiple of 8) works
+// through one contiguous range of the list.
+template <typename real>
+struct BatchDescs {
+  LatDev<real> L[BATCH_DESC_MAX];
+  int start[BATCH_DESC_MAX + 1];
+  int gx[BATCH_DESC_MAX], gz[BATCH_DESC_MAX], zc[BATCH_DESC_MAX];
+  int n;
+};
+static_assert(sizeof(BatchDescs<double>) <= 4000, "descriptors exceed the kernel argument space");
+
 template <typename real, int TX, int TY, int VAR, int WPE>
 __global__ __launch_bounds__((StepShape<real, TX, TY, VAR>::THREADS))
 __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-void k_step_batch(const LatDev<real>* __restrict__ lats, const int4* __restrict__ items,
-                  int nitems, int remap) {
+void k_step_batch(const BatchDescs<real> D, int remap) {
   __shared__ __align__(16) real lds[StepShape<real, TX, TY, VAR>::LDS_REALS];
+  const int nitems = D.start[D.n];
   const int per = (nitems + 7) / 8;
   const int slots = remap ? 8 * per : nitems;
   for (int s = blockIdx.x; s < slots; s += gridDim.x) {
     const int it = remap ? (s & 7) * per + (s >> 3) : s;
     if (it >= nitems) continue;
-    const int4 w = items[it];
-    // the descriptor is read in place (a local copy whose address the
-    // tile's lambdas take would live in scratch memory)
-    const LatDev<real>& L = lats[w.x];
-    const uint32_t zw = (uint32_t)w.w;
-    const int za = (int)(zw & 0xffffu), zlen = (int)((zw >> 16) & 0x7fffu);
-    run_tile<real, TX, TY, VAR>(L, w.y, w.z, za, za + zlen, lds, (zw >> 31) ? -1 : 1);
+    int m = 0;
+    while (m + 1 < D.n && it >= D.start[m + 1]) ++m;
+    const LatDev<real>& L = D.L[m];
+    const int local = it - D.start[m], gz = D.gz[m], gx = D.gx[m];
+    const int bz = local % gz, bx = (local / gz) % gx, by = local / (gz * gx);
+    const int za = bz * D.zc[m];
+    const int zb = min(za + D.zc[m], L.nz);
+    run_tile<real, TX, TY, VAR>(L, bx, by, za, zb, lds, (bz & 1) || gz == 1 ? 1 : -1);
     __syncthreads();  // the next item rewrites the LDS ring
   }
 }
@@ -1381,16 +1400,31 @@ bool variant_writes_moments(int variant) {
 }
 
 template <typename real>
-static hipError_t launch_batch_t(const void* lats, const void* items, int nitems, int grid,
+static hipError_t launch_batch_t(const void* h_descs, int ndesc, const int* h_geo, int grid,
                                  int variant, int remap, hipStream_t s) {
   if (variant < 0 || variant >= variant_count()) return hipErrorInvalidValue;
+  if (ndesc < 1 || ndesc > BATCH_DESC_MAX) return hipErrorInvalidValue;
+  BatchDescs<real> D;
+  std::memset(&D, 0, sizeof(D));
+  std::memcpy(D.L, h_descs, (size_t)ndesc * sizeof(LatDev<real>));
+  D.n = ndesc;
+  D.start[0] = 0;
+  for (int m = 0; m < ndesc; ++m) {
+    const int gx = h_geo[3 * m], gz = h_geo[3 * m + 1], zc = h_geo[3 * m + 2];
+    const LatDev<real>& L = D.L[m];
+    const int gy = (L.ny + kVariants[variant][1] - 1) / kVariants[variant][1];
+    if (gx < 1 || gz < 1 || zc < 1 || gz != (L.nz + zc - 1) / zc) return hipErrorInvalidValue;
+    D.gx[m] = gx;
+    D.gz[m] = gz;
+    D.zc[m] = zc;
+    D.start[m + 1] = D.start[m] + gx * gy * gz;
+  }
   const int tx = kVariants[variant][0], ty = kVariants[variant][1];
   const int var = kVariants[variant][2], wpe = kVariants[variant][3];
 #define SCD_LAUNCHB(a, b, v, w)                                                                 \
   if (tx == a && ty == b && var == v && wpe == w) {                                             \
     hipLaunchKernelGGL((k_step_batch<real, a, b, v, w>), dim3(grid),                            \
-                       dim3(StepShape<real, a, b, v>::THREADS), 0, s,                           \
-                       (const LatDev<real>*)lats, (const int4*)items, nitems, remap);           \
+                       dim3(StepShape<real, a, b, v>::THREADS), 0, s, D, remap);                \
     return hipGetLastError();                                                                   \
   }
   SCD_VARIANTS(SCD_LAUNCHB)
@@ -1398,10 +1432,10 @@ static hipError_t launch_batch_t(const void* lats, const void* items, int nitems
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_batch(int dtype, const void* lats, const void* items, int nitems, int grid,
+hipError_t launch_step_batch(int dtype, const void* h_descs, int ndesc, const int* h_geo, int grid,
                              int variant, int remap, hipStream_t s) {
-  if (dtype == 0) return launch_batch_t<double>(lats, items, nitems, grid, variant, remap, s);
-  return launch_batch_t<float>(lats, items, nitems, grid, variant, remap, s);
+  if (dtype == 0) return launch_batch_t<double>(h_descs, ndesc, h_geo, grid, variant, remap, s);
+  return launch_batch_t<float>(h_descs, ndesc, h_geo, grid, variant, remap, s);
 }
 
 size_t latdev_size(int dtype) { return dtype == 0 ? sizeof(LatDev<double>) : sizeof(LatDev<float>); }

@@ -291,25 +291,35 @@ def young(dtype="f64", steps=20000, grid_steps=20000, with_droplets=True, with_g
 
 
 def sizes(dtype="f32", etas=(0.1, 0.2, 0.3, 0.35), boxes=((128, 40000), (256, 80000)), g=0.16,
-          report_every=10000, stream=None):
+          report_every=10000, stream=None, start="hemisphere", wall="psi", rho_out=0.04):
     """The paper's size/wettability study (Sec. 4): droplets of initial volume
-    (L * 70 / 128)^3 -- 70^3 in the 128^3 box, 140^3 in 256^3 -- started as
-    hemispheres of A (0.7 / 0.04, noise 1e-3, seed 0) on one solid layer at
-    z = 0 (periodic in z, so that layer is also the ceiling), the paper's
-    pseudopotential psi = 1 - exp(-rho), g = 0.16 and the paper's single wall
-    parameter: wall content (0, eta), g_wall = g.  Reports theta_E1/E2 every
-    report_every steps and, per eta, the relative change from the small to
-    the large box."""
+    (L * 70 / 128)^3 -- 70^3 in the 128^3 box, 140^3 in 256^3 -- of A at
+    (0.7, rho_out) in B at (rho_out, 0.7), noise 1e-3, seed 0, on one solid
+    layer at z = 0 (periodic in z, so that layer is also the ceiling), the
+    paper's pseudopotential psi = 1 - exp(-rho), g = 0.16, g_wall = g and
+    the paper's single wall parameter eta.  Readings:
+      start "hemisphere": a hemisphere of that volume on the wall; "cube": a
+        cube of that volume (edge 70 or 140) standing on the wall;
+      wall "psi": wall content (0, eta), which species A feels through
+        psi(eta); "eta": the wall's pseudopotential itself is eta (Huang's
+        G_ads = g eta), i.e. wall content (0, -ln(1 - eta)).
+    Reports theta_E1/E2 every report_every steps and, per eta, the relative
+    change from the small to the large box."""
     stream = stream or torch.cuda.Stream()
     out = {}
     for L_, steps in boxes:
-        vol = (70.0 * L_ / 128.0) ** 3
+        edge = 70.0 * L_ / 128.0
+        vol = edge ** 3
         radius = (3.0 * vol / (2.0 * np.pi)) ** (1.0 / 3.0)
         solid = W.walls_mask(L_, L_, L_, floor=True, ceiling=False)
         nf = fluid_nodes(solid)
         for eta in etas:
-            p = W.params(L_, L_, L_, g, rho_wall=(0.0, eta), psi=1, dtype=dtype)
-            ra, rb = W.cap_densities(L_, L_, L_, radius, 0.5, solid)
+            content = eta if wall == "psi" else -float(np.log1p(-eta))
+            p = W.params(L_, L_, L_, g, rho_wall=(0.0, content), psi=1, dtype=dtype)
+            if start == "cube":
+                ra, rb = W.cube_densities(L_, L_, L_, round(edge), 0, solid, rho_out=rho_out)
+            else:
+                ra, rb = W.cap_densities(L_, L_, L_, radius, 0.5, solid, rho_out=rho_out)
             lat = B.Lattice(p, solid, stream=stream)
             lat.init_equilibrium(ra, rb)
             cfg = W.ca_cfg(L_, L_)
@@ -319,18 +329,28 @@ def sizes(dtype="f32", etas=(0.1, 0.2, 0.3, 0.35), boxes=((128, 40000), (256, 80
                 sec += timed_steps(lat, n, stream)
                 done += n
                 ca = lat.contact_angle(cfg)
-                rec = emit({"exp": "sizes", "box": L_, "eta": eta, "step": done, "radius0": radius,
-                            "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
-                            "mlups": nf * done / sec / 1e6})
+                rec = {"exp": "sizes", "box": L_, "eta": eta, "start": start, "wall": wall,
+                       "rho_out": rho_out, "dtype": dtype, "step": done, "radius0": radius,
+                       "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"], "flags": ca["flags"],
+                       "mlups": nf * done / sec / 1e6}
+                if ca["flags"] & 32:  # no droplet at the column's first fluid node: where is it?
+                    d = lat.density().cpu().numpy()
+                    phi = d[0] - d[1]  # (nz, ny, nx)
+                    col = np.nonzero(phi[1:, cfg["jc"], cfg["ic"]] > 0)[0]
+                    rec["lift"] = {"bottom_on_column": int(col[0]) + 1 if col.size else None,
+                                   "top_on_column": int(col[-1]) + 1 if col.size else None,
+                                   "droplet_nodes": int(np.count_nonzero(phi > 0)),
+                                   "wall_layer_a_nodes": int(np.count_nonzero(phi[1] > 0))}
+                emit(rec)
             out[(L_, eta)] = rec
             del lat
             torch.cuda.empty_cache()
     small, large = boxes[0][0], boxes[-1][0]
     for eta in etas:
-        if (small, eta) in out and (large, eta) in out:
+        if small != large and (small, eta) in out and (large, eta) in out:
             a, b = out[(small, eta)]["theta_e1"], out[(large, eta)]["theta_e1"]
-            emit({"exp": "sizes_change", "eta": eta, "theta_small": a, "theta_large": b,
-                  "relative_change_pct": 100.0 * (b - a) / a})
+            emit({"exp": "sizes_change", "eta": eta, "start": start, "wall": wall,
+                  "theta_small": a, "theta_large": b, "relative_change_pct": 100.0 * (b - a) / a})
     return out
 
 
@@ -388,10 +408,12 @@ def adjoint_cost(reps=20):
     return out
 
 
-def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000):
+def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_every=10000, levels=0):
     """Droplet on a square array of posts (width 6, pitch 12, height 12) in
     a 384 x 384 x 192 box, wall asymmetry -0.3; then one adjoint pass over
-    the last adjoint_steps steps with two-level checkpointing."""
+    the last adjoint_steps steps: one level of checkpoints every K1 steps
+    when its memory fits, else two levels (K2 inside each segment); levels
+    1 or 2 forces the choice."""
     c = W.config_posts(dtype=dtype)
     stream = torch.cuda.Stream()
     L = B.Lattice(c["params"], c["solid"], adjoint=adjoint_steps > 0, stream=stream)
@@ -399,6 +421,10 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
     nf = fluid_nodes(c["solid"])
     best, ms = L.autotune(6, None)
     L.init_equilibrium(c["rho_a"], c["rho_b"])
+    # the mass-drift watchdog at the suggested tolerance of the dtype: the
+    # run goes on, each report says whether the drift exceeds it
+    L.set_mass_watchdog(1e-5 if dtype == "f32" else 1e-10)
+    L.observables(raise_drift=False)  # the reference masses
     emit({"exp": "posts", "fluid_nodes": nf, "tile": list(best), "tune_ms": ms})
     run = steps - adjoint_steps
     done, total_sec = 0, 0.0
@@ -407,14 +433,32 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
         total_sec += timed_steps(L, n, stream)
         done += n
         ca = L.contact_angle(c["ca"])
-        obs = L.observables(raise_nonfinite=False)
+        obs = L.observables(raise_nonfinite=False, raise_drift=False)
         emit({"exp": "posts", "step": L.step_count, "theta_e1": ca["theta_e1"], "theta_e2": ca["theta_e2"],
               "flags": ca["flags"], "mass": list(obs["mass"]), "finite": obs["finite"],
+              "mass_drift": list(obs["drift"]), "drift_flagged": obs["status"] == B.SCD_EDRIFT,
               "mlups": nf * done / total_sec / 1e6})
     out = {"mlups": nf * done / total_sec / 1e6, "steps": done}
     if adjoint_steps > 0:
+        # one level of checkpoints every K1 steps when its memory fits (the
+        # moment cache serves the adjoint, so a segment keeps its moments,
+        # 8 x N reals per step, and only two recomputed states), else a
+        # second level every K2 steps inside each segment.  Only the
+        # multi-plane marches write the moments: the gradient's forward and
+        # recomputed steps use the dtype's default one, at the tuned chunk.
+        L.set_tile(B.variant_index(64, 4, 6, 2) if dtype == "f32" else B.variant_index(32, 4, 7, 1), best[1])
+        state = L.pop_bytes
+        mom = 8 * int(np.prod(L.shape)) * (4 if dtype == "f32" else 8)
+        one_level = (-(-adjoint_steps // K1) + 4) * state + (K1 - 1) * mom
+        free, _ = torch.cuda.mem_get_info()
+        inner = None if one_level < 0.85 * free else K2
+        if levels:  # forced
+            inner = None if levels == 1 else K2
+        emit({"exp": "posts_adjoint_plan", "levels": 1 if inner is None else 2, "K1": K1, "K2": inner,
+              "tile": list(L.tile()),
+              "one_level_bytes": one_level, "free_bytes": free})
         setup = GradSetup(c["params"], c["solid"], None, None, adjoint_steps, K1, c["ca"], 150.0,
-                          lattice=L, inner=K2)
+                          lattice=L, inner=inner)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss = setup.forward()
@@ -422,7 +466,8 @@ def posts(steps=100000, adjoint_steps=1000, dtype="f32", K1=100, K2=10, report_e
         g = setup.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out.update(emit({"exp": "posts_adjoint", "steps": adjoint_steps, "theta_e2": setup.theta, "loss": loss,
+        out.update(emit({"exp": "posts_adjoint", "steps": adjoint_steps, "levels": 1 if inner is None else 2,
+                         "theta_e2": setup.theta, "loss": loss,
                          "grad": g, "forward_s": t1 - t0, "backward_s": t2 - t1,
                          "backward_over_forward": (t2 - t1) / (t1 - t0)}))
     return out
@@ -438,6 +483,11 @@ def main():
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-grid", action="store_true", help="young: skip the 693-system grid")
+    ap.add_argument("--start", default="hemisphere", choices=["hemisphere", "cube"], help="sizes")
+    ap.add_argument("--wall", default="psi", choices=["psi", "eta"], help="sizes")
+    ap.add_argument("--rho-out", type=float, default=0.04, help="sizes: minority density")
+    ap.add_argument("--etas", default=None, help="sizes: comma-separated wall parameters")
+    ap.add_argument("--levels", type=int, default=0, help="posts: checkpoint levels (0: one if it fits)")
     a = ap.parse_args()
     if a.what == "sweep":
         sweep(a.dtype or "f64", a.steps or 20000, a.sweep_box)
@@ -449,13 +499,14 @@ def main():
             boxes = tuple(b for b in boxes if b[0] == a.box)
         if a.steps:
             boxes = tuple((b[0], a.steps) for b in boxes)
-        sizes(a.dtype or "f32", boxes=boxes)
+        etas = tuple(float(e) for e in a.etas.split(",")) if a.etas else (0.1, 0.2, 0.3, 0.35)
+        sizes(a.dtype or "f32", etas=etas, boxes=boxes, start=a.start, wall=a.wall, rho_out=a.rho_out)
     elif a.what == "young":
         young(a.dtype or "f64", a.steps or 20000, with_grid=not a.no_grid)
     elif a.what == "adjoint":
         adjoint_cost()
     else:
-        posts(a.steps or 100000, a.adjoint_steps, a.dtype or "f32")
+        posts(a.steps or 100000, a.adjoint_steps, a.dtype or "f32", levels=a.levels)
 
 
 if __name__ == "__main__":

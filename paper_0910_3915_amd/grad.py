@@ -45,14 +45,15 @@ class GradSetup:
         self.ckpt = torch.empty((nseg,) + shape, dtype=dt, device=dev)
         if self.K2:
             self.mid = torch.empty(((self.K + self.K2 - 1) // self.K2,) + shape, dtype=dt, device=dev)
-            self.seg = torch.empty((self.K2,) + shape, dtype=dt, device=dev)
-        else:
-            self.seg = torch.empty((self.K,) + shape, dtype=dt, device=dev)
         self.lam = torch.empty((2,) + shape, dtype=dt, device=dev)
-        seg_len = self.K2 or self.K
+        self.seg_len = self.K2 or self.K
         self.mom_cache = None
-        if moment_cache and seg_len > 1:
-            self.mom_cache = torch.empty((seg_len - 1, 8) + self.lat.shape, dtype=dt, device=dev)
+        if moment_cache and self.seg_len > 1:
+            self.mom_cache = torch.empty((self.seg_len - 1, 8) + self.lat.shape, dtype=dt, device=dev)
+        # recomputed states of one segment: sized at each backward pass for
+        # the step variant then in use (two buffers when the moment cache
+        # serves the adjoint, else one per recomputed step)
+        self.seg = torch.empty((0,) + shape, dtype=dt, device=dev)
         self.theta = float("nan")
         self.start = None if rho_a is not None else self.lat.get_state()
 
@@ -91,6 +92,12 @@ class GradSetup:
         return list(g)
 
     def _sweep(self, g):
+        n = ctypes.c_int64()
+        B.check(B.lib().scd_ckpt_seg_states(self.lat.h, self.seg_len, ctypes.byref(n)))
+        need = max(n.value, 1)
+        if self.seg.shape[0] != need:
+            self.seg = None
+            self.seg = torch.empty((need, self.lat.pop_numel), dtype=self.lat.dtype, device=self.lat.device)
         if self.K2:
             B.check(B.lib().scd_ckpt_backward2(self.lat.h, self.nsteps, self.K, self.K2, B._ptr(self.ckpt),
                                                B._ptr(self.mid), B._ptr(self.seg), B._ptr(self.lam),

@@ -100,6 +100,41 @@ def test_mixed_member_tiles_equal_sequential():
         assert torch.equal(B.view(i).get_state().cpu(), L.get_state().cpu()), (i, tl[picks[i]])
 
 
+def test_cache_blocked_sets_equal_sequential():
+    """Members packed into cache-blocking sets (two sets, then one member per
+    set), stepped an odd number of steps eagerly and from a captured graph,
+    evolve bit for bit as each lattice stepped alone: only the order of the
+    launches changes."""
+    announce("batch: cache-blocking sets, f32, 32 steps")
+    cases = _members("f32")
+    s = torch.cuda.Stream()
+    B = scd.Batch([c["params"] for c in cases], [c["solid"] for c in cases], stream=s)
+    var = scd.variant_index(64, 4, 6, 2)
+    B.set_tile(var, 8, 0)
+    for i, c in enumerate(cases):
+        B.init_equilibrium(i, c["rho_a"], c["rho_b"])
+    # about 9.5, 5.7 and 6.3 MB of state: the first two members share a set
+    B.set_blocking(16 << 20)
+    assert B.blocking() == (16 << 20, 2)
+    B.step(7)
+    B.graph_capture(10)
+    B.graph_replay(2)
+    B.set_blocking(1)
+    assert B.blocking() == (1, 3)
+    B.step(5)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        L = scd.Lattice(c["params"], c["solid"])
+        L.set_tile(var, 8)
+        L.init_equilibrium(c["rho_a"], c["rho_b"])
+        L.step(32)
+        v = B.view(i)
+        assert v.step_count == 32
+        assert torch.equal(v.get_state().cpu(), L.get_state().cpu()), i
+    B.set_blocking(0)
+    assert B.blocking() == (0, 1)
+
+
 def test_autotune_keeps_results(tmp_path):
     c = W.droplet_case(48, 40, 24, 9.0, 0.12, 0.1)
     L = scd.Lattice(c["params"], c["solid"])

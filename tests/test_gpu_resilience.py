@@ -63,3 +63,39 @@ def test_wall_entries_are_never_read(case):
     assert runs[0][1]["mass"] == runs[1][1]["mass"] and runs[1][1]["finite"]
     assert runs[0][2]["theta_e1"] == runs[1][2]["theta_e1"] or (
         np.isnan(runs[0][2]["theta_e1"]) and np.isnan(runs[1][2]["theta_e1"]))
+
+
+def test_mass_drift_watchdog():
+    """The watchdog measures each species' relative mass change since the
+    first observables call after the state was set, flags it exactly when it
+    exceeds the tolerance (the tolerance is set from the measured drift
+    itself, so the case is forced from the host), and a new state resets
+    the reference."""
+    announce("mass-drift watchdog: f32, 2000 steps")
+    c = W.droplet_case(40, 32, 24, 8.0, 0.12, -0.2, dtype="f32")
+    L = scd.Lattice(c["params"], c["solid"])
+    L.init_equilibrium(c["rho_a"], c["rho_b"])
+    o0 = L.observables()
+    assert o0["drift"] == (0.0, 0.0)
+    L.step(2000)
+    L.set_mass_watchdog(0.0)  # measure only; the reference stays
+    o1 = L.observables()
+    for a in range(2):
+        assert o1["drift"][a] == pytest.approx((o1["mass"][a] - o0["mass"][a]) / o0["mass"][a], rel=1e-12, abs=0)
+    worst = max(abs(v) for v in o1["drift"])
+    assert worst <= 1e-5  # FP32 rounding only
+    if worst > 0:
+        L.set_mass_watchdog(0.5 * worst)
+        with pytest.raises(scd.ScdError) as e:
+            L.observables()
+        assert e.value.status == scd.SCD_EDRIFT
+        o = L.observables(raise_drift=False)
+        assert o["status"] == scd.SCD_EDRIFT and o["drift"] == o1["drift"]
+    L.set_mass_watchdog(2.0 * worst + 1e-30)
+    assert L.observables()["status"] == scd.SCD_OK
+    # a state set from outside is the new reference
+    L.set_mass_watchdog(1e-30)
+    L.set_state(L.get_state(), step=0)
+    assert L.observables()["drift"] == (0.0, 0.0)
+    with pytest.raises(scd.ScdError):
+        L.set_mass_watchdog(-1.0)

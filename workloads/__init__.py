@@ -76,6 +76,25 @@ def cap_densities(nx, ny, nz, radius, z_wall, solid, rho_in=0.7, rho_out=0.04,
     return rho_a, rho_b
 
 
+def cube_densities(nx, ny, nz, side, z_wall, solid, rho_in=0.7, rho_out=0.04, noise=1e-3, seed=0):
+    """A cube of A with edge ``side`` standing on the wall top z_wall,
+    centred on the column (nx/2, ny/2): nodes with |x - nx/2| < side/2,
+    |y - ny/2| < side/2 and z_wall < z <= z_wall + side."""
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    h = side / 2.0
+    inside = (np.abs(x - nx / 2.0) < h) & (np.abs(y - ny / 2.0) < h) & (z > z_wall) & (z <= z_wall + side)
+    rho_a = np.where(inside, rho_in, rho_out).astype(np.float64)
+    rho_b = np.where(inside, rho_out, rho_in).astype(np.float64)
+    if noise:
+        rng = np.random.default_rng(seed)
+        rho_a = rho_a + rng.uniform(-noise, noise, size=rho_a.shape)
+        rho_b = rho_b + rng.uniform(-noise, noise, size=rho_b.shape)
+    solid = np.asarray(solid).astype(bool)
+    rho_a[solid] = 0.0
+    rho_b[solid] = 0.0
+    return rho_a, rho_b
+
+
 def sphere_densities(n, radius, rho_in=0.7, rho_out=0.04, center=None):
     """Free droplet of A in a fully periodic cube (no walls)."""
     if center is None:
