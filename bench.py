@@ -351,6 +351,8 @@ def batched_vs_sequential(scd, W, torch, stream, steps=10000, graph_steps=100, s
             "sequential_default_steps": seq_default_steps,
             "sequential_interleaved_mlups": round(nf / ts_inter / 1e6, 1),
             "speedup": round(min(ts_default, ts_tuned) / per_step_b, 3),
+            "speedup_vs_sequential_default": round(ts_default / per_step_b, 3),
+            "speedup_vs_interleaved": round(ts_inter / per_step_b, 3),
             "theta": {"droplets_compared": len(both),
                       "no_droplet_both": sum(1 for a, b in zip(th_b, th_s) if a is None and b is None),
                       "no_droplet_one_side": sum(1 for a, b in zip(th_b, th_s) if (a is None) != (b is None)),

@@ -114,7 +114,11 @@ def test_gradient_workload_full_size_matches_finite_differences():
         setup.apply_params(vm)
         fm = setup.forward()
         fd = (fp - fm) / (2 * h)
+        announce(f"gradient: component {i} adjoint {g[i]:.6e} central difference {fd:.6e}")
+        # against the largest component, and each component against itself
+        # (the five components lie within a factor 5 of each other here)
         assert abs(fd - g[i]) <= 1e-4 * np.max(np.abs(g)), (i, fd, g[i])
+        assert abs(fd - g[i]) <= 5e-4 * abs(g[i]), (i, fd, g[i])
 
 
 def test_two_level_checkpoints_match_one_level():
