@@ -42,7 +42,9 @@ def build(verbose=False):
         failed = [s for s, p in procs if p.wait() != 0]
         if failed:
             raise RuntimeError("hipcc failed on " + ", ".join(failed))
-        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+        # roctx: the entry points' trace ranges (rocprofv3 --marker-trace)
+        cmd = ([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs +
+               ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", LIB + ".tmp"])
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

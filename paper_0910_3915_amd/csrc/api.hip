@@ -3,6 +3,7 @@
 // ping-pong buffers, observables read-back, the checkpointed adjoint driver,
 // HIP graph capture, the tile autotuner and the batched launch.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -18,6 +19,18 @@
 
 #include "kernels.hpp"
 #include "scdrop.h"
+
+// A roctx range around an entry point (host side: the enqueue, or the whole
+// call where it synchronises), visible in rocprofv3 --marker-trace; without
+// a profiler attached a push and a pop cost a few nanoseconds.
+namespace {
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace
 
 using namespace scd;
 
@@ -360,6 +373,7 @@ scd_status scd_init_equilibrium(scd_lattice* h, const double* d_rho_a, const dou
 }
 
 scd_status scd_step(scd_lattice* h, int64_t nsteps) {
+  TraceRange trace_("scd_step");
   if (!h) return fail(SCD_EINVAL, "NULL handle");
   if (nsteps < 0) return fail(SCD_EINVAL, "nsteps < 0");
   return enqueue_steps(h, nsteps);
@@ -419,6 +433,7 @@ scd_status scd_pull_copy(scd_lattice* h) {
 }
 
 scd_status scd_pressure_tensor(scd_lattice* h, double* d_P) {
+  TraceRange trace_("scd_pressure_tensor");
   if (!h || !d_P) return fail(SCD_EINVAL, "NULL argument");
   HIPCHK(launch_pressure(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz, h->ph,
                          h->wd(h->wl.rho), d_P, h->stream));
@@ -427,6 +442,7 @@ scd_status scd_pressure_tensor(scd_lattice* h, double* d_P) {
 
 scd_status scd_surface_tension_z(scd_lattice* h, double* d_P, double* h_gamma,
                                  double* h_profile) {
+  TraceRange trace_("scd_surface_tension_z");
   if (!h || !d_P || !h_gamma) return fail(SCD_EINVAL, "NULL argument");
   scd_status st = scd_pressure_tensor(h, d_P);
   if (st) return st;
@@ -453,6 +469,7 @@ scd_status scd_radial_tension_axes(scd_lattice* h, double* d_P, const double* h_
                                    int32_t periodic, double rmax, int32_t nbins,
                                    double* h_profile, double* h_phi_profile, double* h_Rs,
                                    double* h_gamma) {
+  TraceRange trace_("scd_radial_tension_axes");
   if (!h || !d_P || !h_center || !h_Rs || !h_gamma) return fail(SCD_EINVAL, "NULL argument");
   if (periodic < 0 || periodic > 7) return fail(SCD_EINVAL, "periodic mask must be in [0, 7]");
   const int maxb = RED_BLOCKS * RED_STRIDE / 3;
@@ -514,6 +531,7 @@ scd_status scd_density(scd_lattice* h, double* d_rho) {
 }
 
 scd_status scd_observables(scd_lattice* h, scd_obs* out) {
+  TraceRange trace_("scd_observables");
   if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
   HIPCHK(launch_observables(h->p.dtype, h->pop[h->cur], h->links(), h->p.nx, h->p.ny, h->p.nz,
                             h->wd(h->wl.partials), h->wd(h->wl.result), h->stream));
@@ -559,6 +577,7 @@ scd_status scd_mass_drift(const scd_lattice* h, double* h_drift) {
 }
 
 scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out) {
+  TraceRange trace_("scd_contact_angle");
   if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
@@ -573,6 +592,7 @@ scd_status scd_contact_angle(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out)
 }
 
 scd_status scd_contact_angle_static(scd_lattice* h, const scd_ca_cfg* cfg, scd_ca* out) {
+  TraceRange trace_("scd_contact_angle_static");
   if (!h || !out) return fail(SCD_EINVAL, "NULL argument");
   scd_status st = check_cfg(h, cfg);
   if (st) return st;
@@ -643,6 +663,7 @@ scd_status scd_adjoint_read(scd_lattice* h, double* h_acc) {
 
 scd_status scd_adjoint_step(scd_lattice* h, const void* d_state_t, const void* d_lam_in,
                             void* d_lam_out, double* h_dparams) {
+  TraceRange trace_("scd_adjoint_step");
   if (!h || !d_state_t || !d_lam_in || !d_lam_out) return fail(SCD_EINVAL, "NULL argument");
   if (!(h->p.flags & SCD_WITH_ADJOINT))
     return fail(SCD_EUNSUPPORTED, "lattice created without SCD_WITH_ADJOINT");
@@ -662,6 +683,7 @@ static const double kRad2Deg = 57.295779513082320876798154814105;
 scd_status scd_ckpt_forward(scd_lattice* h, const double* d_rho_a, const double* d_rho_b,
                             int64_t nsteps, int64_t K, void* d_ckpt, const scd_ca_cfg* cfg,
                             double target_deg, double* h_out) {
+  TraceRange trace_("scd_ckpt_forward");
   if (!h || !d_ckpt || !h_out) return fail(SCD_EINVAL, "NULL argument");
   if (nsteps < 1 || K < 1) return fail(SCD_EINVAL, "nsteps and ckpt_every must be >= 1");
   if ((d_rho_a == nullptr) != (d_rho_b == nullptr))
@@ -784,6 +806,7 @@ static scd_status backward_start(scd_lattice* h, int64_t nsteps, int64_t K, cons
 scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const void* d_ckpt,
                              void* d_seg, void* d_lam, const scd_ca_cfg* cfg, double target_deg,
                              double* h_grad) {
+  TraceRange trace_("scd_ckpt_backward");
   if (!h || !d_seg || !h_grad) return fail(SCD_EINVAL, "NULL argument");
   void* lam[2];
   scd_status st = backward_start(h, nsteps, K, d_ckpt, d_lam, cfg, target_deg, lam);
@@ -802,6 +825,7 @@ scd_status scd_ckpt_backward(scd_lattice* h, int64_t nsteps, int64_t K, const vo
 scd_status scd_ckpt_backward2(scd_lattice* h, int64_t nsteps, int64_t K1, int64_t K2,
                               const void* d_ckpt, void* d_mid, void* d_seg, void* d_lam,
                               const scd_ca_cfg* cfg, double target_deg, double* h_grad) {
+  TraceRange trace_("scd_ckpt_backward2");
   if (!h || !d_mid || !d_seg || !h_grad) return fail(SCD_EINVAL, "NULL argument");
   if (K2 < 1 || K2 > K1) return fail(SCD_EINVAL, "need 1 <= K2 <= K1");
   void* lam[2];
@@ -925,6 +949,7 @@ static bool cache_lookup(const char* path, const std::string& key, int* best, do
 
 scd_status scd_autotune(scd_lattice* h, int32_t steps_per_trial, const char* cache_path,
                         int32_t* best, double* best_ms) {
+  TraceRange trace_("scd_autotune");
   if (!h || !best || !best_ms) return fail(SCD_EINVAL, "NULL argument");
   if (steps_per_trial < 2) return fail(SCD_EINVAL, "steps_per_trial must be >= 2");
   const std::string key = tune_key(h);
@@ -1011,6 +1036,7 @@ scd_status scd_graph_capture(scd_lattice* h, int64_t nsteps) {
 }
 
 scd_status scd_graph_replay(scd_lattice* h, int64_t reps) {
+  TraceRange trace_("scd_graph_replay");
   if (!h) return fail(SCD_EINVAL, "NULL handle");
   if (!h->gexec) return fail(SCD_EINVAL, "no captured graph");
   if (h->cur != h->graph_cur) return fail(SCD_EINVAL, "buffer parity changed since capture");
@@ -1325,6 +1351,7 @@ scd_status scd_batch_member_tile(const scd_batch* b, int32_t i, int32_t* variant
 }
 
 scd_status scd_batch_step(scd_batch* b, int64_t nsteps) {
+  TraceRange trace_("scd_batch_step");
   if (!b) return fail(SCD_EINVAL, "NULL handle");
   if (nsteps < 0) return fail(SCD_EINVAL, "nsteps < 0");
   return batch_enqueue(b, nsteps);
@@ -1386,6 +1413,7 @@ static std::vector<long long> cache_list(const char* path, const std::string& ke
 
 scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char* cache_path,
                               int32_t* best, double* best_ms) {
+  TraceRange trace_("scd_batch_autotune");
   if (!b || !best || !best_ms) return fail(SCD_EINVAL, "NULL argument");
   if (steps_per_trial < 2) return fail(SCD_EINVAL, "steps_per_trial must be >= 2");
   // key: member count, a hash of the member shapes, dtype, device, variant count
@@ -1594,6 +1622,7 @@ scd_status scd_batch_blocking(const scd_batch* b, int64_t* set_bytes, int32_t* n
 }
 
 scd_status scd_batch_graph_replay(scd_batch* b, int64_t reps) {
+  TraceRange trace_("scd_batch_graph_replay");
   if (!b) return fail(SCD_EINVAL, "NULL handle");
   if (!b->gexec) return fail(SCD_EINVAL, "no captured graph");
   if (b->parity != b->graph_parity) return fail(SCD_EINVAL, "buffer parity changed since capture");
