@@ -859,6 +859,267 @@ __device__ __forceinline__ void step_tile_multi(const LatDev<real>& L, int bx, i
 }
 
 // ---------------------------------------------------------------------------
+// The species-split multi-plane march on a tile of TY rows in which each
+// thread owns RR nodes of one column, TY / RR rows apart.  A TX x TY tile
+// then runs on the threads of a TX x (TY / RR) one, so that a taller tile,
+// with fewer halo nodes per interior node, fits the registers of one wave
+// per SIMD: a 32 x 8 tile has 84 halo nodes for 256 interior ones (0.33
+// per node) against 76 for 128 (0.59) on 32 x 4.  Per iteration the loads
+// of G planes of all RR rows are in flight together, as in the G-plane march.
+template <typename real, int TX, int TY, int G, int RR>
+__device__ __forceinline__ void step_tile_rows(const LatDev<real>& L, int bx, int by, int za,
+                                               int zb, real* __restrict__ lds, int dir = 1) {
+  using T = SplitTile<TX, TY>;  // geometry of the whole tile (ring, halo)
+  constexpr int TYT = TY / RR;  // thread rows
+  static_assert(TY % RR == 0, "rows per thread must divide the tile height");
+  constexpr int NT = 2 * TX * TYT;
+  constexpr int HPT = (T::TASKS + NT - 1) / NT;
+  constexpr int RS = MultiRing<G>::RS;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int a = lane >> 5;
+  const int node = wave * 32 + (lane & 31);
+  const int tx = node % TX, ty0 = node / TX;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, N = L.N;
+  const int x0 = bx * TX, y0 = by * TY;
+  bool active[RR], need[RR];
+  int xs[3], ys[RR][3], pos[RR];
+  axis3(wrap_index(x0 + tx, nx), nx, xs);
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int ty = ty0 + r * TYT;
+    active[r] = (x0 + tx) < nx && (y0 + ty) < ny;
+    // lanes past the first column or row beyond a partial tile's edge feed
+    // no active node: they act as wall nodes (no pulls, never collided)
+    need[r] = (x0 + tx) <= nx && (y0 + ty) <= ny;
+    axis3(wrap_index(y0 + ty, ny), ny, ys[r]);
+    pos[r] = (ty + 1) * T::LX + (tx + 1);
+  }
+  auto ring = [&](int zr, int c) { return lds + ((zr & (RS - 1)) * 2 + c) * T::P; };
+
+  // halo tasks dealt wave-major over the NT threads, as in the G-plane march
+  int hx[HPT][3], hy[HPT][3], hpos[HPT], hsp[HPT];
+  bool hval[HPT];
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int sl = tid + h * NT;
+    const int q = (sl >> 6) * 32 + (sl & 31);
+    const bool valid = q < T::R;
+    hsp[h] = (sl >> 5) & 1;
+    int lx, ly;
+    if (q < T::LX) { ly = -1; lx = q - 1; }
+    else if (q < 2 * T::LX) { ly = TY; lx = q - T::LX - 1; }
+    else if (q < 2 * T::LX + TY) { lx = -1; ly = q - 2 * T::LX; }
+    else { lx = TX; ly = q - 2 * T::LX - TY; }
+    hval[h] = valid && x0 + lx <= nx && y0 + ly <= ny;
+    if (!hval[h]) { lx = 0; ly = 0; }
+    axis3(wrap_index(x0 + lx, nx), nx, hx[h]);
+    axis3(wrap_index(y0 + ly, ny), ny, hy[h]);
+    hpos[h] = (ly + 1) * T::LX + (lx + 1);
+  }
+
+  constexpr uint32_t S = sizeof(real);
+  const uint32_t NS = PBLK * S, PS = L.geo.pb * (Q * PBLK) * S;
+  uint32_t col[RR][3][3], hcol[HPT][3][3];
+  int cidx[RR];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    column_offsets<real>(L.geo, xs, ys[r], nx, col[r]);
+    cidx[r] = ys[r][1] * nx + xs[1];
+  }
+  const char* __restrict__ sbase = reinterpret_cast<const char*>(L.src + (size_t)a * L.geo.sp);
+  const char* __restrict__ hbase[HPT];
+  int hidx[HPT];
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    column_offsets<real>(L.geo, hx[h], hy[h], nx, hcol[h]);
+    hbase[h] = reinterpret_cast<const char*>(L.src + (size_t)hsp[h] * L.geo.sp);
+    hidx[h] = hy[h][1] * nx + hx[h][1];
+  }
+
+  const int M = zb - za;
+  auto zof = [&](int j) { return dir > 0 ? za - 1 + j : zb - j; };
+  auto links_of = [&](int j, uint32_t(&li)[RR], uint32_t(&lh)[HPT]) {
+    const int zn = wrap_index(zof(j), nz) * nx * ny;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) li[r] = need[r] ? L.links[zn + cidx[r]] : SELF_SOLID;
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) lh[h] = hval[h] ? L.links[zn + hidx[h]] : SELF_SOLID;
+  };
+
+  const real gab = L.ph.gab;
+  const int psi_form = L.ph.psi_form;
+  const real ew0 = L.ph.gw[1] * L.ph.psiw[0];
+  const real ew1 = L.ph.gw[0] * L.ph.psiw[1];
+  auto e_of = [&](int sp, bool wall, real rho) {
+    return wall ? (sp ? ew1 : ew0) : gab * psi_of(psi_form, rho);
+  };
+
+  auto issue = [&](int j, const uint32_t(&li)[RR], const uint32_t(&lh)[HPT], real(&n)[RR][19],
+                   real(&hm)[HPT][19]) {
+    int zs[3];
+    axis3(wrap_index(zof(j), nz), nz, zs);
+    const uint32_t zo[3] = {(uint32_t)zs[0] * PS, (uint32_t)zs[1] * PS, (uint32_t)zs[2] * PS};
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+      if (!(li[r] & SELF_SOLID)) pull19_cols<real>(sbase, NS, col[r], zo, li[r], n[r]);
+#pragma unroll
+    for (int h = 0; h < HPT; ++h)
+      if (!(lh[h] & SELF_SOLID)) pull19_cols<real>(hbase[h], NS, hcol[h], zo, lh[h], hm[h]);
+  };
+  auto reduce = [&](int j, const uint32_t(&li)[RR], const uint32_t(&lh)[HPT], const real(&n)[RR][19],
+                    const real(&hm)[HPT][19]) {
+    const int zr = zof(j);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const bool wall = li[r] & SELF_SOLID;
+      real rho = 0;
+      if (!wall) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) rho += n[r][k];
+      }
+      ring(zr, 1 - a)[pos[r]] = e_of(a, wall, rho);
+      if (L.mom_out && j >= 1 && j <= M && active[r])
+        L.mom_out[(size_t)a * N + (size_t)zr * nx * ny + cidx[r]] = rho;
+    }
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+      if (!hval[h]) continue;
+      const bool hw = lh[h] & SELF_SOLID;
+      real rh = 0;
+      if (!hw) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) rh += hm[h][k];
+      }
+      ring(zr, 1 - hsp[h])[hpos[h]] = e_of(hsp[h], hw, rh);
+    }
+  };
+
+  const Phys<real>& ph = L.ph;
+  auto collide = [&](int zc, int r, const real(&nc)[19], bool solid) {
+    real rho, jx, jy, jz;
+    moments(nc, rho, jx, jy, jz);
+    const real rho_o = __shfl_xor(rho, 32, 64), jx_o = __shfl_xor(jx, 32, 64);
+    const real jy_o = __shfl_xor(jy, 32, 64), jz_o = __shfl_xor(jz, 32, 64);
+    if (!active[r] || solid) return;
+    const int cx = cidx[r];
+    if (L.mom_out) {
+      real* m = L.mom_out + (size_t)(2 + 3 * a) * N + (size_t)zc * nx * ny + cx;
+      m[0] = jx;
+      m[N] = jy;
+      m[2 * (size_t)N] = jz;
+    }
+    const real* sm = ring(zc - 1, a);
+    const real* s0 = ring(zc, a);
+    const real* sp = ring(zc + 1, a);
+    const int ps = pos[r];
+    real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      const real* sl = CZ[k] < 0 ? sm : (CZ[k] > 0 ? sp : s0);
+      const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+      const real e = w * sl[ps + CY[k] * T::LX + CX[k]];
+      if (CX[k]) sx += CX[k] * e;
+      if (CY[k]) sy += CY[k] * e;
+      if (CZ[k]) sz += CZ[k] * e;
+    }
+    const real psi_a = psi_of(ph.psi_form, rho);
+    const real rA = a ? rho_o : rho, rB = a ? rho : rho_o;
+    const real jAx = a ? jx_o : jx, jBx = a ? jx : jx_o;
+    const real jAy = a ? jy_o : jy, jBy = a ? jy : jy_o;
+    const real jAz = a ? jz_o : jz, jBz = a ? jz : jz_o;
+    const real itA = ph.inv_tau[0], itB = ph.inv_tau[1];
+    const real iR = real(1) / (rA * itA + rB * itB);
+    const real shf = ph.tau[a] / rho;
+    const real ux = (jAx * itA + jBx * itB) * iR + shf * (-psi_a * sx);
+    const real uy = (jAy * itA + jBy * itB) * iR + shf * (-psi_a * sy);
+    const real uz = (jAz * itA + jBz * itB) * iR + shf * (-psi_a * sz);
+    const real uu = ux * ux + uy * uy + uz * uz;
+    const real it = ph.inv_tau[a];
+    const uint32_t iS = (uint32_t)zc * PS + col[r][1][1];
+    char* __restrict__ out = reinterpret_cast<char*>(L.dst + (size_t)a * L.geo.sp);
+    real moving = 0;
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const int o = k + 1;
+      const real sdot = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+      real fk, fo;
+      equilibrium_pair(real(WEIGHT[k]) * rho, sdot, uu, fk, fo);
+      moving += fk + fo;
+      st_off_nt<real>(out, (uint32_t)k * NS + iS, nc[k] + (fk - nc[k]) * it);
+      st_off_nt<real>(out, (uint32_t)o * NS + iS, nc[o] + (fo - nc[o]) * it);
+    }
+    const real eq0 = rho - moving;
+    st_off_nt<real>(out, iS, nc[0] + (eq0 - nc[0]) * it);
+  };
+
+  // n[g][r]: plane c + g of row r (n[0]: the plane collided first)
+  real n[G + 1][RR][19];
+  real hm[G][HPT][19];
+  bool solid[G + 1][RR];
+  uint32_t lk[G][RR], lkh[G][HPT];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int r = 0; r < RR; ++r) lk[g][r] = SELF_SOLID;
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) lkh[g][h] = SELF_SOLID;
+  }
+  {
+    uint32_t l0[RR], lh0[HPT], l1[RR], lh1[HPT];
+    links_of(0, l0, lh0);
+    links_of(1, l1, lh1);
+    // plane 0 only feeds e values; its halo buffer is reduced before plane
+    // 1 reuses it (with G = 1 there is one)
+    issue(0, l0, lh0, n[1], hm[0]);
+    reduce(0, l0, lh0, n[1], hm[0]);
+    issue(1, l1, lh1, n[0], hm[G - 1]);
+    reduce(1, l1, lh1, n[0], hm[G - 1]);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) solid[0][r] = (l1[r] & SELF_SOLID) != 0;
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (2 + g <= M + 1) links_of(2 + g, lk[g], lkh[g]);
+  for (int c = 1; c <= M; c += G) {
+    uint32_t u[G][RR], uh[G][HPT];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int r = 0; r < RR; ++r) u[g][r] = lk[g][r];
+#pragma unroll
+      for (int h = 0; h < HPT; ++h) uh[g][h] = lkh[g][h];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + g <= M + 1) issue(c + 1 + g, u[g], uh[g], n[1 + g], hm[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + G + g <= M + 1) links_of(c + 1 + G + g, lk[g], lkh[g]);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + 1 + g <= M + 1) {
+        reduce(c + 1 + g, u[g], uh[g], n[1 + g], hm[g]);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) solid[1 + g][r] = (u[g][r] & SELF_SOLID) != 0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (c + g <= M) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) collide(zof(c + g), r, n[g][r], solid[g][r]);
+      }
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) n[0][r][k] = n[G][r][k];
+      solid[0][r] = solid[G][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Software-pipelined species-split z-march.  Iteration p issues the loads of
 // plane p (interior and halo), collides plane p - 2 while they are in
 // flight, then turns plane p into e values.  Collision of plane c needs e
@@ -1050,19 +1311,23 @@ constexpr int VAR_JOINT = 5;     // species split, streaming stores, all loads o
 constexpr int VAR_DUAL = 6;      // species split, two planes per iteration
 constexpr int VAR_TRIPLE = 7;    // species split, three planes per iteration
 constexpr int VAR_QUAD = 8;      // species split, four planes per iteration
+constexpr int VAR_ROWS2 = 9;     // two planes per iteration, two rows per thread
+constexpr int VAR_ROWS1 = 10;    // one plane per iteration, two rows per thread
 
 template <typename real, int TX, int TY, int VAR>
 struct StepShape {
+  static constexpr bool ROWS = VAR == VAR_ROWS2 || VAR == VAR_ROWS1;  // two rows per thread
   static constexpr bool SPLIT =
       VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT ||
-      VAR == VAR_DUAL || VAR == VAR_TRIPLE || VAR == VAR_QUAD;
-  static constexpr int THREADS = SPLIT ? 2 * TX * TY : TX * TY;
+      VAR == VAR_DUAL || VAR == VAR_TRIPLE || VAR == VAR_QUAD || ROWS;
+  static constexpr int THREADS = ROWS ? TX * TY : SPLIT ? 2 * TX * TY : TX * TY;
   static constexpr int LDS_REALS =
-      VAR == VAR_DUAL     ? 2 * MultiRing<2>::RS * SplitTile<TX, TY>::P
-      : VAR == VAR_TRIPLE ? 2 * MultiRing<3>::RS * SplitTile<TX, TY>::P
-      : VAR == VAR_QUAD   ? 2 * MultiRing<4>::RS * SplitTile<TX, TY>::P
-      : SPLIT             ? 8 * SplitTile<TX, TY>::P
-                          : 8 * Tile<TX, TY>::P;
+      VAR == VAR_DUAL || VAR == VAR_ROWS2 ? 2 * MultiRing<2>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_TRIPLE                 ? 2 * MultiRing<3>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_QUAD                   ? 2 * MultiRing<4>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_ROWS1                  ? 2 * MultiRing<1>::RS * SplitTile<TX, TY>::P
+      : SPLIT                             ? 8 * SplitTile<TX, TY>::P
+                                          : 8 * Tile<TX, TY>::P;
 };
 
 template <typename real, int TX, int TY, int VAR>
@@ -1080,6 +1345,10 @@ __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, 
     step_tile_multi<real, TX, TY, 3>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_QUAD)
     step_tile_multi<real, TX, TY, 4>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_ROWS2)
+    step_tile_rows<real, TX, TY, 2, 2>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_ROWS1)
+    step_tile_rows<real, TX, TY, 1, 2>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -1336,7 +1605,7 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
   X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
   X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 5, 1) X(32, 4, 5, 2) X(32, 8, 5, 2) \
   X(64, 4, 5, 2) X(32, 8, 6, 2) X(32, 4, 6, 1) X(64, 4, 6, 2) X(32, 4, 7, 1) X(64, 4, 7, 2) \
-  X(32, 4, 8, 1)
+  X(32, 4, 8, 1) X(32, 8, 9, 1) X(32, 8, 10, 1) X(64, 8, 9, 2) X(64, 8, 10, 2)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},
@@ -1396,7 +1665,7 @@ hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* li
 bool variant_writes_moments(int variant) {
   if (variant < 0 || variant >= variant_count()) return false;
   const int var = kVariants[variant][2];
-  return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD;
+  return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD || var == VAR_ROWS2 || var == VAR_ROWS1;
 }
 
 template <typename real>
