@@ -1512,7 +1512,7 @@ scd_status scd_batch_autotune(scd_batch* b, int32_t steps_per_trial, const char*
     return SCD_OK;
   };
   double bms = 1e30;
-  std::vector<int> bmem(b->n, b->variant), bzc(b->n, b->zc);
+  std::vector<int> bmem = b->mvar, bzc = b->mzc;  // the current tiles until a trial beats them
   int bgrid = 0;
   int64_t bsb = 0;
   auto trial = [&](const std::vector<int>& mv, const std::vector<int>& mz, int grid,

@@ -1313,19 +1313,21 @@ constexpr int VAR_TRIPLE = 7;    // species split, three planes per iteration
 constexpr int VAR_QUAD = 8;      // species split, four planes per iteration
 constexpr int VAR_ROWS2 = 9;     // two planes per iteration, two rows per thread
 constexpr int VAR_ROWS1 = 10;    // one plane per iteration, two rows per thread
+constexpr int VAR_ROWS4 = 11;    // one plane per iteration, four rows per thread
 
 template <typename real, int TX, int TY, int VAR>
 struct StepShape {
-  static constexpr bool ROWS = VAR == VAR_ROWS2 || VAR == VAR_ROWS1;  // two rows per thread
+  static constexpr int RR = VAR == VAR_ROWS4 ? 4 : (VAR == VAR_ROWS2 || VAR == VAR_ROWS1) ? 2 : 1;
+  static constexpr bool ROWS = RR > 1;  // several rows per thread
   static constexpr bool SPLIT =
       VAR == VAR_SPLIT || VAR == VAR_SPLIT_NT || VAR == VAR_PIPE || VAR == VAR_JOINT ||
       VAR == VAR_DUAL || VAR == VAR_TRIPLE || VAR == VAR_QUAD || ROWS;
-  static constexpr int THREADS = ROWS ? TX * TY : SPLIT ? 2 * TX * TY : TX * TY;
+  static constexpr int THREADS = ROWS ? 2 * TX * TY / RR : SPLIT ? 2 * TX * TY : TX * TY;
   static constexpr int LDS_REALS =
       VAR == VAR_DUAL || VAR == VAR_ROWS2 ? 2 * MultiRing<2>::RS * SplitTile<TX, TY>::P
       : VAR == VAR_TRIPLE                 ? 2 * MultiRing<3>::RS * SplitTile<TX, TY>::P
       : VAR == VAR_QUAD                   ? 2 * MultiRing<4>::RS * SplitTile<TX, TY>::P
-      : VAR == VAR_ROWS1                  ? 2 * MultiRing<1>::RS * SplitTile<TX, TY>::P
+      : VAR == VAR_ROWS1 || VAR == VAR_ROWS4 ? 2 * MultiRing<1>::RS * SplitTile<TX, TY>::P
       : SPLIT                             ? 8 * SplitTile<TX, TY>::P
                                           : 8 * Tile<TX, TY>::P;
 };
@@ -1349,6 +1351,8 @@ __device__ __forceinline__ void run_tile(const LatDev<real>& L, int bx, int by, 
     step_tile_rows<real, TX, TY, 2, 2>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_ROWS1)
     step_tile_rows<real, TX, TY, 1, 2>(L, bx, by, za, zb, lds, dir);
+  else if constexpr (VAR == VAR_ROWS4)
+    step_tile_rows<real, TX, TY, 1, 4>(L, bx, by, za, zb, lds, dir);
   else if constexpr (VAR == VAR_PIPE)
     step_tile_pipe<real, TX, TY>(L, bx, by, za, zb, lds);
   else
@@ -1605,7 +1609,7 @@ hipError_t launch_fill(int dtype, void* p, size_t n, double v, hipStream_t s) {
   X(64, 4, 0, 1) X(32, 8, 0, 1) X(64, 4, 1, 1) X(32, 4, 2, 2) X(32, 8, 2, 2) X(32, 4, 3, 2) \
   X(64, 4, 3, 2) X(32, 8, 3, 2) X(32, 4, 4, 1) X(32, 4, 5, 1) X(32, 4, 5, 2) X(32, 8, 5, 2) \
   X(64, 4, 5, 2) X(32, 8, 6, 2) X(32, 4, 6, 1) X(64, 4, 6, 2) X(32, 4, 7, 1) X(64, 4, 7, 2) \
-  X(32, 4, 8, 1) X(32, 8, 9, 1) X(32, 8, 10, 1) X(64, 8, 9, 2) X(64, 8, 10, 2)
+  X(32, 4, 8, 1) X(32, 8, 9, 1) X(32, 8, 10, 1) X(64, 8, 9, 2) X(64, 8, 10, 2) X(32, 16, 11, 1)
 
 static const int kVariants[][4] = {
 #define SCD_ROW(a, b, v, w) {a, b, v, w},
@@ -1665,7 +1669,8 @@ hipError_t launch_step(int dtype, const void* src, void* dst, const uint32_t* li
 bool variant_writes_moments(int variant) {
   if (variant < 0 || variant >= variant_count()) return false;
   const int var = kVariants[variant][2];
-  return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD || var == VAR_ROWS2 || var == VAR_ROWS1;
+  return var == VAR_DUAL || var == VAR_TRIPLE || var == VAR_QUAD || var == VAR_ROWS2 ||
+         var == VAR_ROWS1 || var == VAR_ROWS4;
 }
 
 template <typename real>

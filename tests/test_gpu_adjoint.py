@@ -158,6 +158,25 @@ def test_gradient_from_current_state_matches_oracle():
     assert np.allclose(g, go, rtol=1e-8, atol=0), (g, go)
 
 
+def test_cached_segments_keep_two_states():
+    """With the moment cache covering a segment and a step variant that
+    writes the moments, a recomputed segment needs two state buffers (the
+    adjoint of a cached state reads nothing else of it); a variant that
+    writes none needs one per recomputed step, and the gradients agree."""
+    c = _tiny(0.1)
+    nsteps, K, target = 30, 10, 110.0
+    s = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target)
+    s.forward()
+    g2 = s.backward()
+    assert s.seg.shape[0] == 2
+    r = scd.GradSetup(c["params"], c["solid"], c["rho_a"], c["rho_b"], nsteps, K, c["ca"], target)
+    r.lat.set_tile(scd.variant_index(64, 4, 0, 1), 4)
+    r.forward()
+    gk = r.backward()
+    assert r.seg.shape[0] == K - 1
+    assert np.allclose(g2, gk, rtol=1e-9, atol=0), (g2, gk)  # the variants round differently
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("inner", [None, 4])
 def test_moment_cache_gives_the_same_gradient(dtype, inner):
