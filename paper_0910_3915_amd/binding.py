@@ -504,7 +504,8 @@ def variant_index(tx, ty, zmarch, waves):
 
 
 class Batch:
-    """Many lattices stepped together by one persistent launch per step."""
+    """Many lattices stepped together: one launch per group of members and
+    step, cache-blocked in sets (scd_batch_* in include/scdrop.h)."""
 
     def __init__(self, params_list, solids, device="cuda", stream=None):
         self.device = torch.device(device)
