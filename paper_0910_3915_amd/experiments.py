@@ -495,8 +495,8 @@ def main():
         fit(a.dtype or "f64", a.iters, a.steps or 2000)
     elif a.what == "sizes":
         boxes = ((128, 40000), (256, 80000))
-        if a.box:
-            boxes = tuple(b for b in boxes if b[0] == a.box)
+        if a.box:  # one box edge (the paper checks 32, 64, 128 and 256)
+            boxes = ((a.box, 80000 if a.box > 128 else 40000),)
         if a.steps:
             boxes = tuple((b[0], a.steps) for b in boxes)
         etas = tuple(float(e) for e in a.etas.split(",")) if a.etas else (0.1, 0.2, 0.3, 0.35)
