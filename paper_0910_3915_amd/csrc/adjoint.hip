@@ -22,24 +22,6 @@
 
 namespace scd {
 
-// Streaming with bounce-back as in the forward step, addressed with element
-// offsets from the state base.
-template <typename real>
-__device__ __forceinline__ void pull38_adj(const real* __restrict__ src, const PopGeo& g,
-                                           const int (&xs)[3], const int (&ys)[3],
-                                           const int (&zs)[3], int nx, uint32_t lb,
-                                           real (&n)[38]) {
-  const uint32_t self = pop_slot(g, zs[1], ys[1] * nx + xs[1]);
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    const uint32_t j = pop_slot(g, zs[1 - CZ[k]], ys[1 - CY[k]] * nx + xs[1 - CX[k]]);
-    const bool bb = (lb >> OPP[k]) & 1u;
-    const size_t off = bb ? self + (uint32_t)OPP[k] * PBLK : j + (uint32_t)k * PBLK;
-    n[k] = src[off];
-    n[Q + k] = src[(size_t)g.sp + off];
-  }
-}
-
 template <int NV>
 __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -78,7 +60,7 @@ __global__ __launch_bounds__(256) void k_stream_moments(const real* __restrict__
       axis3((i / nx) % ny, ny, ys);
       axis3(i / (nx * ny), nz, zs);
       real n[38];
-      pull38_adj(C, pg, xs, ys, zs, nx, lb, n);
+      pull38(C, pg, xs, ys, zs, nx, lb, n);  // 32-bit byte offsets, as the step's pulls
       moments(&n[0], r[0], j[0][0], j[0][1], j[0][2]);
       moments(&n[Q], r[1], j[1][0], j[1][1], j[1][2]);
     }
