@@ -221,6 +221,160 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
           accumulate ? partials[blockIdx.x * RED_STRIDE + c] + gp[c] : gp[c];
 }
 
+// The same local pass with the two species of a node on the two halves of
+// a wave: lanes 0-31 take species A of 32 consecutive nodes, lanes 32-63
+// species B of the same nodes, and the partners exchange the few values
+// that couple the species (the other species' density and momentum, and its
+// velocity adjoint) through __shfl_xor(., 32).  A lane then holds lambda' of
+// one species and the neighbour densities of the other (the force on
+// species a is built from psi^b of the neighbours), half the registers of
+// the pass above, so that the FP64 pass runs at two waves per SIMD instead
+// of one.  The arithmetic of every node and species is the same, in the
+// same order; only the wall-parameter partials are summed in another order.
+template <typename real>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_adj_local_split(
+    const real* __restrict__ jm, const real* __restrict__ lam, const uint32_t* __restrict__ links,
+    const real* __restrict__ rhof, int nx, int ny, int nz, Phys<real> ph, real* __restrict__ qf,
+    real* __restrict__ df, real* __restrict__ ef, double* __restrict__ partials, int accumulate) {
+  __shared__ double sh[5 * 16];
+  const int N = nx * ny * nz;
+  const PopGeo pg = pop_geo(nx, ny, nz);
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 5, b = 1 - a;
+  const int waves = (gridDim.x * blockDim.x) >> 6;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  double gp[5] = {0, 0, 0, 0, 0};  // rho_wall_A, rho_wall_B, g_ab, g_wall_A, g_wall_B
+  constexpr uint32_t SZ = sizeof(real);
+  const char* __restrict__ rother = reinterpret_cast<const char*>(rhof + (size_t)b * N);
+  const char* __restrict__ lown = reinterpret_cast<const char*>(lam + (size_t)a * pg.sp);
+  // every lane of a wave runs the same number of iterations, so that the
+  // partners of a node are always active together
+  for (int base = wave * 32; base < N; base += waves * 32) {
+    const int i = base + (lane & 31);
+    const bool in = i < N;
+    const uint32_t lb = in ? links[i] : SELF_SOLID;
+    const bool fluid = !(lb & SELF_SOLID);
+    int xs[3], ys[3], zs[3];
+    const int ic = in ? i : 0;
+    axis3(ic % nx, nx, xs);
+    axis3((ic / nx) % ny, ny, ys);
+    axis3(ic / (nx * ny), nz, zs);
+    const uint32_t si = pop_slot(pg, zs[1], ys[1] * nx + xs[1]);
+    // own species' moments and lambda'; the other species' neighbour
+    // densities (a wall neighbour's entry is a valid zero, its wall content
+    // is selected below)
+    real rho_s = 0, js[3] = {0, 0, 0};
+    real lm[Q], nb[Q];
+    if (fluid) {
+      rho_s = rhof[(size_t)a * N + i];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) js[d] = jm[(size_t)(3 * a + d) * N + i];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) lm[k] = ld_off<real>(lown, (si + (uint32_t)k * PBLK) * SZ);
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        nb[k] = ld_off<real>(rother, (uint32_t)nbr_index(xs, ys, zs, nx, ny, CX[k], CY[k], CZ[k]) * SZ);
+    }
+    // the partner's density and momentum (both lanes of a node take part)
+    const real rho_o = __shfl_xor(rho_s, 32, 64);
+    const real jo0 = __shfl_xor(js[0], 32, 64), jo1 = __shfl_xor(js[1], 32, 64),
+               jo2 = __shfl_xor(js[2], 32, 64);
+    real rho[2], j[2][3];
+    rho[a] = rho_s;
+    rho[b] = rho_o;
+    j[a][0] = js[0]; j[a][1] = js[1]; j[a][2] = js[2];
+    j[b][0] = jo0; j[b][1] = jo1; j[b][2] = jo2;
+    // S^a = sum_k W_k G^a(y) psi^b(y) c_k and Wv = sum over the wall
+    // neighbours of W_k c_k
+    real S[3] = {0, 0, 0}, Wv[3] = {0, 0, 0};
+    if (fluid) {
+#pragma unroll
+      for (int k = 1; k < Q; ++k) {
+        const bool wall = (lb >> k) & 1u;
+        const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
+        const real e = wall ? w * ph.gw[a] * ph.psiw[b] : w * ph.gab * psi_of(ph.psi_form, nb[k]);
+        const real wv = wall ? w : real(0);
+        Wv[0] += CX[k] * wv; Wv[1] += CY[k] * wv; Wv[2] += CZ[k] * wv;
+        S[0] += CX[k] * e; S[1] += CY[k] * e; S[2] += CZ[k] * e;
+      }
+    }
+    const real psi_s = psi_of(ph.psi_form, rho[a]);
+    real F[3];
+    for (int d = 0; d < 3; ++d) F[d] = -psi_s * S[d];
+    const real Rt = rho[0] * ph.inv_tau[0] + rho[1] * ph.inv_tau[1];
+    real up[3], u[3];
+    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) / Rt;
+    for (int d = 0; d < 3; ++d) u[d] = up[d] + ph.tau[a] * F[d] / rho[a];
+
+    // transpose of the collision of species a
+    real drho = 0, du[3] = {0, 0, 0};
+    if (fluid) {
+      const real ux = u[0], uy = u[1], uz = u[2];
+      const real uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const real g = lm[k] * ph.inv_tau[a];
+        const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+        const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
+                       real(4.5) * s * s * s - real(4.5) * uu * s;
+        const real Ps = real(3) + real(9) * s + real(13.5) * s * s - real(4.5) * uu;
+        const real Pq = real(-1.5) - real(4.5) * s;
+        const real wg = real(WEIGHT[k]) * g;
+        drho += wg * P;
+        const real wr = wg * rho[a];
+        du[0] += wr * (Ps * CX[k] + real(2) * Pq * ux);
+        du[1] += wr * (Ps * CY[k] + real(2) * Pq * uy);
+        du[2] += wr * (Ps * CZ[k] + real(2) * Pq * uz);
+      }
+    }
+    // transpose of u^a = u' + tau^a F^a / rho^a, u' = J / R; dup sums the
+    // velocity adjoints of both species, in species order
+    real dF[3], Fdu = 0;
+    for (int d = 0; d < 3; ++d) {
+      dF[d] = ph.tau[a] / rho[a] * du[d];
+      Fdu += F[d] * du[d];
+    }
+    drho += -ph.tau[a] * Fdu / (rho[a] * rho[a]);
+    const real duo0 = __shfl_xor(du[0], 32, 64), duo1 = __shfl_xor(du[1], 32, 64),
+               duo2 = __shfl_xor(du[2], 32, 64);
+    const real duA[3] = {a ? duo0 : du[0], a ? duo1 : du[1], a ? duo2 : du[2]};
+    const real duB[3] = {a ? du[0] : duo0, a ? du[1] : duo1, a ? du[2] : duo2};
+    real dup[3];
+    for (int d = 0; d < 3; ++d) {
+      dup[d] = 0;
+      dup[d] += duA[d];
+      dup[d] += duB[d];
+    }
+    if (!in) continue;
+    if (!fluid) {
+      for (int d = 0; d < 3; ++d) {
+        qf[(size_t)(a * 3 + d) * N + i] = 0;
+        ef[(size_t)(a * 3 + d) * N + i] = 0;
+      }
+      df[(size_t)a * N + i] = 0;
+      continue;
+    }
+    const real dupu = dup[0] * up[0] + dup[1] * up[1] + dup[2] * up[2];
+    const real f = ph.inv_tau[a] / Rt;
+    for (int d = 0; d < 3; ++d) ef[(size_t)(a * 3 + d) * N + i] = dup[d] * f;
+    drho += -dupu * f;
+    // transpose of the force: local part and the gradient of the wall
+    // parameters (the fluid neighbours' part, the g_ab gradient, is taken in
+    // the transposed stencil)
+    const real dpsi_self = -(dF[0] * S[0] + dF[1] * S[1] + dF[2] * S[2]);
+    for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi_s * dF[d];
+    df[(size_t)a * N + i] = drho + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
+    const double t = (double)(-psi_s * (dF[0] * Wv[0] + dF[1] * Wv[1] + dF[2] * Wv[2]));
+    gp[3 + a] += (double)ph.psiw[b] * t;
+    gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
+  }
+  block_sum_adj<5>(gp, sh);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 5; ++c)
+      partials[blockIdx.x * RED_STRIDE + c] =
+          accumulate ? partials[blockIdx.x * RED_STRIDE + c] + gp[c] : gp[c];
+}
+
 // D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b:
 // the transposed force stencil as a pass of its own (the FP32 path; the FP64
 // path does it inside the push-stream pass)
@@ -390,8 +544,15 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
     hipLaunchKernelGGL(k_stream_moments<real>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256),
                        0, s, C, links, rhof, jf, nx, ny, nz);
   }
-  hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, jm,
-                     lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
+  // FP64: the species-split local pass at two waves per SIMD (142.8 against
+  // 150.7 us on 128 x 128 x 64); FP32 fits three waves per SIMD with both
+  // species on one lane, and the split runs slower there (91.3 against 77.4)
+  if constexpr (sizeof(real) == 8)
+    hipLaunchKernelGGL(k_adj_local_split<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s,
+                       jm, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
+  else
+    hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, jm,
+                       lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
   // FP64 adds the transposed stencil inside the push pass (one fewer sweep
   // of D); in FP32 the gathers slow that pass more than the sweep costs.
   // The pass that gathers the stencil has one row of g_ab partials per
