@@ -9,14 +9,15 @@
 //      force from the neighbours' post-stream densities, velocities) and
 //      transpose the collision (Eq. Equil), the velocity shift and the local
 //      part of the force; store q^a = psi^a dL/dF^a, D^a = dL/drho^a and
-//      E^a = dL/dj^a, and accumulate the gradient of the wall parameters;
+//      the vector e = dL/du' / R, from which dL/dj^a = e / tau^a, and
+//      accumulate the gradient of the wall parameters;
 //   2. per node: add the transposed force stencil, i.e. the gather
 //      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) to D (FP32: as
 //      a pass of its own), with the same gather giving the g_ab gradient
 //      (-psi^b(y) times it, summed), then stream transposed with
 //      bounce-back, as a push of
-//      dL/dn_k = D + E . c_k + (1 - 1/tau) lambda'_k to x - c_k (or to the
-//      node itself on the opposite velocity next to a wall).
+//      dL/dn_k = D + (e / tau) . c_k + (1 - 1/tau) lambda'_k to x - c_k (or
+//      to the node itself on the opposite velocity next to a wall).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -37,6 +38,63 @@ __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
       for (int w = 0; w < nw; ++w) s += sh[j * 16 + w];
       v[j] = s;
     }
+}
+
+// dL/drho and dL/du of the equilibrium term n^eq_k(rho, u) / tau of one
+// species' collision (Eq. Equil, cubic in u), given lambda' of its 19
+// populations.  With G_k = W_k lambda'_k, s_k = c_k . u, a = 3 - 9/2 u.u and
+// b = 1 - 3/2 u.u:
+//   tau dL/drho = sum_k G_k (b + s_k (a + s_k (9/2 + 9/2 s_k))),
+//   tau dL/du_d = rho [sum_k G_k c_kd (a + s_k (9 + 27/2 s_k)) - m u_d],
+//   m = sum_k G_k (3 + 9 s_k),
+// taking s_k and the c_kd terms only along the components c_k moves in
+// (c_kd = +-1 or 0).  The velocity sums start at -0, which the first
+// addition leaves exactly.  The velocities are taken one at a time, so that
+// each lambda'_k is released once used.
+template <typename real>
+__device__ __forceinline__ void equil_adj(const real (&lm)[Q], real inv_tau, real rho,
+                                          const real (&u)[3], real& drho, real (&du)[3]) {
+  const real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const real a = real(3) - real(4.5) * uu, b = real(1) - real(1.5) * uu;
+  const real G0 = real(WEIGHT[0]) * lm[0];
+  real dr = G0 * b, m = real(3) * G0;
+  real v[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v[d] = real(-0.0);
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    const int c[3] = {CX[k], CY[k], CZ[k]};
+    const real G = real(WEIGHT[k]) * lm[k];
+    real s = real(-0.0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (c[d]) s += c[d] > 0 ? u[d] : -u[d];
+    dr += G * (b + s * (a + s * (real(4.5) + real(4.5) * s)));
+    m += G * (real(3) + real(9) * s);
+    const real w = G * (a + s * (real(9) + real(13.5) * s));
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (c[d]) v[d] += c[d] > 0 ? w : -w;
+  }
+  drho = dr * inv_tau;
+  const real rt = rho * inv_tau;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) du[d] = rt * (v[d] - m * u[d]);
+}
+
+// v = sum over the 18 moving velocities of e_k c_k, taken over the opposite
+// pairs as (e_k - e_{k+1}) c_k along the components c_k moves in.
+template <typename real>
+__device__ __forceinline__ void pair_moment(const real (&e)[Q], real (&v)[3]) {
+  v[0] = v[1] = v[2] = real(-0.0);
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const int c[3] = {CX[k], CY[k], CZ[k]};
+    const real t = e[k] - e[k + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (c[d]) v[d] += c[d] > 0 ? t : -t;
+  }
 }
 
 // Post-stream densities and momenta of the state a reverse step reads:
@@ -100,7 +158,8 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
     const uint32_t lb = links[i];
     if (lb & SELF_SOLID) {
-      for (int c = 0; c < 6; ++c) { qf[(size_t)c * N + i] = 0; ef[(size_t)c * N + i] = 0; }
+      for (int c = 0; c < 6; ++c) qf[(size_t)c * N + i] = 0;
+      for (int d = 0; d < 3; ++d) ef[(size_t)d * N + i] = 0;
       df[i] = 0;
       df[(size_t)N + i] = 0;
       continue;
@@ -130,8 +189,6 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
     // the wall parameters).  Every neighbour's densities are loaded (a wall
     // node's field entry is a valid zero) and the wall content selected
     // afterwards, so the loads carry no branch between them.
-    real S[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    real Wv[3] = {0, 0, 0};
     real nA[Q], nB[Q];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
@@ -139,65 +196,51 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       nA[k] = ld_off<real>(rbase[0], yo);
       nB[k] = ld_off<real>(rbase[1], yo);
     }
+    real eA[Q], eB[Q], wv[Q];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const bool wall = (lb >> k) & 1u;
       const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-      const real eA = wall ? w * ph.gw[0] * ph.psiw[1] : w * ph.gab * psi_of(ph.psi_form, nB[k]);
-      const real eB = wall ? w * ph.gw[1] * ph.psiw[0] : w * ph.gab * psi_of(ph.psi_form, nA[k]);
-      const real wv = wall ? w : real(0);
-      Wv[0] += CX[k] * wv; Wv[1] += CY[k] * wv; Wv[2] += CZ[k] * wv;
-      S[0][0] += CX[k] * eA; S[0][1] += CY[k] * eA; S[0][2] += CZ[k] * eA;
-      S[1][0] += CX[k] * eB; S[1][1] += CY[k] * eB; S[1][2] += CZ[k] * eB;
+      eA[k] = wall ? w * ph.gw[0] * ph.psiw[1] : w * ph.gab * psi_of(ph.psi_form, nB[k]);
+      eB[k] = wall ? w * ph.gw[1] * ph.psiw[0] : w * ph.gab * psi_of(ph.psi_form, nA[k]);
+      wv[k] = wall ? w : real(0);
     }
+    real S[2][3], Wv[3];
+    pair_moment(eA, S[0]);
+    pair_moment(eB, S[1]);
+    pair_moment(wv, Wv);
     real F[2][3];
     for (int a = 0; a < 2; ++a)
       for (int d = 0; d < 3; ++d) F[a][d] = -psi[a] * S[a][d];
+    // three reciprocals serve every quotient below
     const real Rt = rho[0] * ph.inv_tau[0] + rho[1] * ph.inv_tau[1];
+    const real iRt = real(1) / Rt;
+    const real ir[2] = {real(1) / rho[0], real(1) / rho[1]};
+    const real tr[2] = {ph.tau[0] * ir[0], ph.tau[1] * ir[1]};  // tau^a / rho^a
     real up[3], u[2][3];
-    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) / Rt;
+    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) * iRt;
     for (int a = 0; a < 2; ++a)
-      for (int d = 0; d < 3; ++d) u[a][d] = up[d] + ph.tau[a] * F[a][d] / rho[a];
+      for (int d = 0; d < 3; ++d) u[a][d] = up[d] + tr[a] * F[a][d];
 
     // transpose of the collision C' = n (1 - 1/tau) + n^eq(rho, u) / tau
-    real drho[2] = {0, 0}, du[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    real drho[2], du[2][3];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const real ux = u[a][0], uy = u[a][1], uz = u[a][2];
-      const real uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const real g = lm[a][k] * ph.inv_tau[a];
-        const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
-        const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
-                       real(4.5) * s * s * s - real(4.5) * uu * s;
-        const real Ps = real(3) + real(9) * s + real(13.5) * s * s - real(4.5) * uu;
-        const real Pq = real(-1.5) - real(4.5) * s;
-        const real wg = real(WEIGHT[k]) * g;
-        drho[a] += wg * P;
-        const real wr = wg * rho[a];
-        du[a][0] += wr * (Ps * CX[k] + real(2) * Pq * ux);
-        du[a][1] += wr * (Ps * CY[k] + real(2) * Pq * uy);
-        du[a][2] += wr * (Ps * CZ[k] + real(2) * Pq * uz);
-      }
-    }
+    for (int a = 0; a < 2; ++a) equil_adj(lm[a], ph.inv_tau[a], rho[a], u[a], drho[a], du[a]);
     // transpose of u^a = u' + tau^a F^a / rho^a, u' = J / R
     real dF[2][3], dup[3] = {0, 0, 0};
     for (int a = 0; a < 2; ++a) {
       real Fdu = 0;
       for (int d = 0; d < 3; ++d) {
-        dF[a][d] = ph.tau[a] / rho[a] * du[a][d];
+        dF[a][d] = tr[a] * du[a][d];
         Fdu += F[a][d] * du[a][d];
         dup[d] += du[a][d];
       }
-      drho[a] += -ph.tau[a] * Fdu / (rho[a] * rho[a]);
+      drho[a] += -tr[a] * Fdu * ir[a];
     }
     const real dupu = dup[0] * up[0] + dup[1] * up[1] + dup[2] * up[2];
-    for (int a = 0; a < 2; ++a) {
-      const real f = ph.inv_tau[a] / Rt;
-      for (int d = 0; d < 3; ++d) ef[(size_t)(a * 3 + d) * N + i] = dup[d] * f;
-      drho[a] += -dupu * f;
-    }
+    // dL/dj^a = dup / (tau^a R): one vector serves both species
+    for (int d = 0; d < 3; ++d) ef[(size_t)d * N + i] = dup[d] * iRt;
+    for (int a = 0; a < 2; ++a) drho[a] += -dupu * (ph.inv_tau[a] * iRt);
     // transpose of the force: local part and the gradient of the wall
     // parameters (the fluid neighbours' part, the g_ab gradient, is taken in
     // the transposed stencil, which gathers the same pair products)
@@ -288,33 +331,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // neighbours of W_k c_k
     real S[3] = {0, 0, 0}, Wv[3] = {0, 0, 0};
     if (fluid) {
+      real e[Q], wv[Q];
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         const bool wall = (lb >> k) & 1u;
         const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-        const real e = wall ? w * ph.gw[a] * ph.psiw[b] : w * ph.gab * psi_of(ph.psi_form, nb[k]);
-        const real wv = wall ? w : real(0);
-        Wv[0] += CX[k] * wv; Wv[1] += CY[k] * wv; Wv[2] += CZ[k] * wv;
-        S[0] += CX[k] * e; S[1] += CY[k] * e; S[2] += CZ[k] * e;
+        e[k] = wall ? w * ph.gw[a] * ph.psiw[b] : w * ph.gab * psi_of(ph.psi_form, nb[k]);
+        wv[k] = wall ? w : real(0);
       }
+      pair_moment(e, S);
+      pair_moment(wv, Wv);
     }
     const real psi_s = psi_of(ph.psi_form, rho[a]);
     real F[3];
     for (int d = 0; d < 3; ++d) F[d] = -psi_s * S[d];
+    // two reciprocals serve every quotient below
     const real Rt = rho[0] * ph.inv_tau[0] + rho[1] * ph.inv_tau[1];
+    const real iRt = real(1) / Rt, ir = real(1) / rho[a];
+    const real tr = ph.tau[a] * ir;  // tau^a / rho^a
     real up[3], u[3];
-    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) / Rt;
-    for (int d = 0; d < 3; ++d) u[d] = up[d] + ph.tau[a] * F[d] / rho[a];
+    for (int d = 0; d < 3; ++d) up[d] = (j[0][d] * ph.inv_tau[0] + j[1][d] * ph.inv_tau[1]) * iRt;
+    for (int d = 0; d < 3; ++d) u[d] = up[d] + tr * F[d];
 
     // transpose of the collision of species a
     real drho = 0, du[3] = {0, 0, 0};
     if (fluid) {
-      const real ux = u[0], uy = u[1], uz = u[2];
-      const real uu = ux * ux + uy * uy + uz * uz;
+      // the terms of equil_adj in their first form, one velocity at a time
+      // (the moment form needs more registers than two waves per SIMD
+      // leave this kernel)
+      const real uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
+        const int c[3] = {CX[k], CY[k], CZ[k]};
         const real g = lm[k] * ph.inv_tau[a];
-        const real s = CX[k] * ux + CY[k] * uy + CZ[k] * uz;
+        real s = real(-0.0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (c[d]) s += c[d] > 0 ? u[d] : -u[d];
         const real P = real(1) + real(3) * s + real(4.5) * s * s - real(1.5) * uu +
                        real(4.5) * s * s * s - real(4.5) * uu * s;
         const real Ps = real(3) + real(9) * s + real(13.5) * s * s - real(4.5) * uu;
@@ -322,19 +375,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const real wg = real(WEIGHT[k]) * g;
         drho += wg * P;
         const real wr = wg * rho[a];
-        du[0] += wr * (Ps * CX[k] + real(2) * Pq * ux);
-        du[1] += wr * (Ps * CY[k] + real(2) * Pq * uy);
-        du[2] += wr * (Ps * CZ[k] + real(2) * Pq * uz);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          du[d] += wr * ((c[d] ? (c[d] > 0 ? Ps : -Ps) : real(-0.0)) + real(2) * Pq * u[d]);
       }
     }
     // transpose of u^a = u' + tau^a F^a / rho^a, u' = J / R; dup sums the
     // velocity adjoints of both species, in species order
     real dF[3], Fdu = 0;
     for (int d = 0; d < 3; ++d) {
-      dF[d] = ph.tau[a] / rho[a] * du[d];
+      dF[d] = tr * du[d];
       Fdu += F[d] * du[d];
     }
-    drho += -ph.tau[a] * Fdu / (rho[a] * rho[a]);
+    drho += -tr * Fdu * ir;
     const real duo0 = __shfl_xor(du[0], 32, 64), duo1 = __shfl_xor(du[1], 32, 64),
                duo2 = __shfl_xor(du[2], 32, 64);
     const real duA[3] = {a ? duo0 : du[0], a ? duo1 : du[1], a ? duo2 : du[2]};
@@ -347,17 +400,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     }
     if (!in) continue;
     if (!fluid) {
-      for (int d = 0; d < 3; ++d) {
-        qf[(size_t)(a * 3 + d) * N + i] = 0;
-        ef[(size_t)(a * 3 + d) * N + i] = 0;
-      }
+      for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = 0;
+      ef[(size_t)a * N + i] = 0;
+      if (a == 0) ef[2 * (size_t)N + i] = 0;
       df[(size_t)a * N + i] = 0;
       continue;
     }
     const real dupu = dup[0] * up[0] + dup[1] * up[1] + dup[2] * up[2];
-    const real f = ph.inv_tau[a] / Rt;
-    for (int d = 0; d < 3; ++d) ef[(size_t)(a * 3 + d) * N + i] = dup[d] * f;
-    drho += -dupu * f;
+    // dL/dj^a = dup / (tau^a R): one vector for both species, its
+    // components x and y stored by the lanes of species A and B, z by A
+    ef[(size_t)a * N + i] = (a ? dup[1] : dup[0]) * iRt;
+    if (a == 0) ef[2 * (size_t)N + i] = dup[2] * iRt;
+    drho += -dupu * (ph.inv_tau[a] * iRt);
     // transpose of the force: local part and the gradient of the wall
     // parameters (the fluid neighbours' part, the g_ab gradient, is taken in
     // the transposed stencil)
@@ -444,7 +498,7 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
 // from q of the other species at the 18 upstream nodes:
 //   D^a(y) = D_local^a(y) + psi'(rho^a(y)) * (-g_ab sum_k W_k q^b(y - c_k) . c_k)
 // (only the components along which c_k moves are loaded: 60 loads).  Then
-// the push: mu_k(y) = D(y) + E(y) . c_k + (1 - 1/tau) lambda'_k(y)
+// the push: mu_k(y) = D(y) + e(y) . c_k / tau + (1 - 1/tau) lambda'_k(y)
 // (= dL/dn_k(y)) goes to lambda_k(y - c_k) when y - c_k is fluid (the
 // forward step pulled n_k(y) from C_k(y - c_k)), and mu_{opp k}(y) goes to
 // lambda_k(y) itself when y + c_k is a wall (the forward step bounced C_k(y)
@@ -478,6 +532,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
     }
     real acc[2] = {0, 0};
     if constexpr (FUSED) stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
+    const real e[3] = {ef[i], ef[(size_t)N + i], ef[2 * (size_t)N + i]};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       real D = df[(size_t)a * N + i];
@@ -486,15 +541,19 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
         D += dpsi_of(ph.psi_form, ra) * (-ph.gab * acc[a]);
         gab[0] -= (double)psi_of(ph.psi_form, ra) * (double)acc[a];
       }
-      const real Ex = ef[(size_t)(a * 3 + 0) * N + i];
-      const real Ey = ef[(size_t)(a * 3 + 1) * N + i];
-      const real Ez = ef[(size_t)(a * 3 + 2) * N + i];
+      const real E[3] = {ph.inv_tau[a] * e[0], ph.inv_tau[a] * e[1], ph.inv_tau[a] * e[2]};
       const real keep = real(1) - ph.inv_tau[a];
       real mu[Q];
 #pragma unroll
-      for (int k = 0; k < Q; ++k)
-        mu[k] = D + Ex * CX[k] + Ey * CY[k] + Ez * CZ[k] +
-                keep * lam[a * (size_t)pg.sp + si + k * PBLK];
+      for (int k = 0; k < Q; ++k) {
+        // D + E . c_k, along the components c_k moves in
+        const int c[3] = {CX[k], CY[k], CZ[k]};
+        real m = D;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (c[d]) m += c[d] > 0 ? E[d] : -E[d];
+        mu[k] = m + keep * lam[a * (size_t)pg.sp + si + k * PBLK];
+      }
       real* __restrict__ oa = out + a * (size_t)pg.sp;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {

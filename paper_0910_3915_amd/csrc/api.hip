@@ -85,7 +85,7 @@ WorkLayout work_layout(const scd_params* p) {
     w.adj_dparams = take(16 * 8);  // [0, 8): last step, [8, 16): accumulator
     w.q = take(6 * N * rs);
     w.d = take(2 * N * rs);
-    w.e = take(6 * N * rs);
+    w.e = take(3 * N * rs);  // dL/du' / R, shared by both species
     w.jm = take(6 * N * rs);  // post-stream momenta of the state a plain reverse step reads
   }
   w.total = off;
