@@ -61,6 +61,41 @@ def test_adjoint_step_matches_oracle(variant):
     assert np.allclose(dp, dpo, rtol=1e-10, atol=1e-10 * np.max(np.abs(dpo)))
 
 
+@pytest.mark.parametrize("variant", ["plain", "post_tau_psi"])
+def test_fp32_adjoint_step_matches_oracle(variant):
+    """The FP32 reverse step (its own local, stencil and push passes) against
+    the oracle's FP64 transpose at the same FP32 state and the same
+    FP32-rounded lambda', so that only the reverse step's own FP32
+    arithmetic differs: every entry within 2e-6 of the largest (measured
+    1.9e-7 and 2.1e-7) and the parameter gradient within 1e-5 of its largest
+    component (measured 2.5e-7 and 8.3e-7)."""
+    c = _tiny()
+    p = dict(c["params"], dtype="f32")
+    solid = c["solid"].copy()
+    if variant == "post_tau_psi":
+        solid[1:4, 3:6, 4:7] = 1
+        p = dict(p, tau=(1.0, 0.8), psi=1, g_wall=(0.09, 0.14))
+    ra, rb = W.cap_densities(16, 16, 12, 5.0, 0.5, solid, noise=0.02, seed=4)
+    announce(f"FP32 adjoint parity: 16x16x12 {variant}")
+    L = scd.Lattice(p, solid, adjoint=True)
+    L.init_equilibrium(ra, rb)
+    L.step(5)
+    st = L.get_state()
+    rng = np.random.default_rng(9)
+    fluid = (solid == 0)[None, None]
+    lam = (rng.normal(size=(2, 19) + solid.shape) * fluid).astype(np.float32)
+    out, dp = L.adjoint_step(st, torch.from_numpy(lam).cuda())
+    Lo = O.Lattice(dict(p, dtype="f64"), solid)
+    lo, dpo = Lo.adjoint_step(O.from_gpu_layout(st.double().cpu().numpy()),
+                              O.from_gpu_layout(lam.astype(np.float64)))
+    g = O.from_gpu_layout(out.double().cpu().numpy())
+    err = np.max(np.abs(g - lo)) / np.max(np.abs(lo))
+    derr = np.max(np.abs(np.array(dp) - dpo)) / np.max(np.abs(dpo))
+    announce(f"FP32 adjoint parity: lambda {err:.3e}, parameter gradient {derr:.3e}")
+    assert err <= 2e-6
+    assert derr <= 1e-5
+
+
 def test_checkpointed_gradient_matches_oracle_and_fd():
     c = _tiny(0.1)
     nsteps, K, target = 50, 7, 120.0
