@@ -105,7 +105,9 @@ constexpr int ADJ_BLOCKS = 8192;  // rows of adjoint partials (workgroups of the
 // into rho_field and the moments from the pulled populations.  acc_partials == nullptr: this step's parameter gradient
 // is summed into dparams_dev[0..5).  Otherwise the per-workgroup partials
 // accumulate in acc_partials (ADJ_BLOCKS x RED_STRIDE doubles, zeroed by the
-// caller) and launch_adjoint_sum reduces them when they are read.
+// caller) and launch_adjoint_sum reduces them when they are read.  Work
+// fields: q_field 6 N, d_field 2 N and e_field 3 N reals (e = dL/du' / R,
+// shared by both species); rho_field 2 N and j_field 6 N.
 hipError_t launch_adjoint(int dtype, const void* state_t, const void* lam_in, void* lam_out,
                           const uint32_t* links, int nx, int ny, int nz, const PhysD& ph,
                           void* rho_field, void* j_field, const void* mom_cached, void* q_field,
