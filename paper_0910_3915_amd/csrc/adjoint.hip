@@ -40,6 +40,15 @@ __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
     }
 }
 
+// The pair forms below take velocity k + 1 as the opposite of k for odd k.
+constexpr bool opposite_pairs_adjacent() {
+  for (int k = 1; k < Q; k += 2)
+    if (OPP[k] != k + 1 || CX[k + 1] != -CX[k] || CY[k + 1] != -CY[k] || CZ[k + 1] != -CZ[k])
+      return false;
+  return true;
+}
+static_assert(opposite_pairs_adjacent(), "velocity k + 1 must be the opposite of odd k");
+
 // dL/drho and dL/du of the equilibrium term n^eq_k(rho, u) / tau of one
 // species' collision (Eq. Equil, cubic in u), given lambda' of its 19
 // populations.  With G_k = W_k lambda'_k, s_k = c_k . u, a = 3 - 9/2 u.u and
