@@ -49,6 +49,28 @@ constexpr bool opposite_pairs_adjacent() {
 }
 static_assert(opposite_pairs_adjacent(), "velocity k + 1 must be the opposite of odd k");
 
+// psi (and psi') of densities with the form tested once, outside any loop:
+// written as one select per value, the exponential of the other form is
+// evaluated for every value whichever form is in use.
+template <typename real, int NV>
+__device__ __forceinline__ void psi_in_place(int form, real (&v)[NV], int k0) {
+  if (form == 1) {
+#pragma unroll
+    for (int k = k0; k < NV; ++k) v[k] = real(1) - exp(-v[k]);
+  }
+}
+template <typename real>
+__device__ __forceinline__ void psi_pair(int form, real rho, real& psi, real& dpsi) {
+  if (form == 1) {
+    const real t = exp(-rho);
+    psi = real(1) - t;
+    dpsi = t;
+  } else {
+    psi = rho;
+    dpsi = real(1);
+  }
+}
+
 // dL/drho and dL/du of the equilibrium term n^eq_k(rho, u) / tau of one
 // species' collision (Eq. Equil, cubic in u), given lambda' of its 19
 // populations.  With G_k = W_k lambda'_k, s_k = c_k . u, a = 3 - 9/2 u.u and
@@ -185,7 +207,9 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
 #pragma unroll
       for (int d = 0; d < 3; ++d) j[a][d] = jm[(size_t)(3 * a + d) * N + i];
     }
-    real psi[2] = {psi_of(ph.psi_form, rho[0]), psi_of(ph.psi_form, rho[1])};
+    real psi[2], dpsi[2];
+    psi_pair(ph.psi_form, rho[0], psi[0], dpsi[0]);
+    psi_pair(ph.psi_form, rho[1], psi[1], dpsi[1]);
     // lambda' of both species, requested before the neighbour densities so
     // that all 74 loads of the node are in flight together
     real lm[2][Q];
@@ -205,13 +229,15 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       nA[k] = ld_off<real>(rbase[0], yo);
       nB[k] = ld_off<real>(rbase[1], yo);
     }
+    psi_in_place(ph.psi_form, nA, 1);  // now psi^A and psi^B of the neighbours
+    psi_in_place(ph.psi_form, nB, 1);
     real eA[Q], eB[Q], wv[Q];
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       const bool wall = (lb >> k) & 1u;
       const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-      eA[k] = wall ? w * ph.gw[0] * ph.psiw[1] : w * ph.gab * psi_of(ph.psi_form, nB[k]);
-      eB[k] = wall ? w * ph.gw[1] * ph.psiw[0] : w * ph.gab * psi_of(ph.psi_form, nA[k]);
+      eA[k] = wall ? w * ph.gw[0] * ph.psiw[1] : w * ph.gab * nB[k];
+      eB[k] = wall ? w * ph.gw[1] * ph.psiw[0] : w * ph.gab * nA[k];
       wv[k] = wall ? w : real(0);
     }
     real S[2][3], Wv[3];
@@ -258,7 +284,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const real* __restrict__ jm,
       const int b = 1 - a;
       const real dpsi_self = -(dF[a][0] * S[a][0] + dF[a][1] * S[a][1] + dF[a][2] * S[a][2]);
       for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi[a] * dF[a][d];
-      df[(size_t)a * N + i] = drho[a] + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
+      df[(size_t)a * N + i] = drho[a] + dpsi[a] * dpsi_self;
       // sum over the wall neighbours of -psi^a W_k dF^a . c_k
       const double t = (double)(-psi[a] * (dF[a][0] * Wv[0] + dF[a][1] * Wv[1] + dF[a][2] * Wv[2]));
       gp[3 + a] += (double)ph.psiw[b] * t;
@@ -340,18 +366,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // neighbours of W_k c_k
     real S[3] = {0, 0, 0}, Wv[3] = {0, 0, 0};
     if (fluid) {
+      psi_in_place(ph.psi_form, nb, 1);  // now psi^b of the neighbours
       real e[Q], wv[Q];
 #pragma unroll
       for (int k = 1; k < Q; ++k) {
         const bool wall = (lb >> k) & 1u;
         const real w = (CX[k] * CX[k] + CY[k] * CY[k] + CZ[k] * CZ[k]) == 1 ? ph.wa : ph.wd;
-        e[k] = wall ? w * ph.gw[a] * ph.psiw[b] : w * ph.gab * psi_of(ph.psi_form, nb[k]);
+        e[k] = wall ? w * ph.gw[a] * ph.psiw[b] : w * ph.gab * nb[k];
         wv[k] = wall ? w : real(0);
       }
       pair_moment(e, S);
       pair_moment(wv, Wv);
     }
-    const real psi_s = psi_of(ph.psi_form, rho[a]);
+    real psi_s, dpsi_s;
+    psi_pair(ph.psi_form, rho[a], psi_s, dpsi_s);
     real F[3];
     for (int d = 0; d < 3; ++d) F[d] = -psi_s * S[d];
     // two reciprocals serve every quotient below
@@ -426,7 +454,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // the transposed stencil)
     const real dpsi_self = -(dF[0] * S[0] + dF[1] * S[1] + dF[2] * S[2]);
     for (int d = 0; d < 3; ++d) qf[(size_t)(a * 3 + d) * N + i] = psi_s * dF[d];
-    df[(size_t)a * N + i] = drho + dpsi_of(ph.psi_form, rho[a]) * dpsi_self;
+    df[(size_t)a * N + i] = drho + dpsi_s * dpsi_self;
     const double t = (double)(-psi_s * (dF[0] * Wv[0] + dF[1] * Wv[1] + dF[2] * Wv[2]));
     gp[3 + a] += (double)ph.psiw[b] * t;
     gp[b] += (double)ph.gw[a] * t * (double)ph.dpsiw[b];
@@ -491,9 +519,10 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
     stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const real rb = rhof[(size_t)b * N + i];
-      df[(size_t)b * N + i] += dpsi_of(ph.psi_form, rb) * (-ph.gab * acc[b]);
-      gab[0] -= (double)psi_of(ph.psi_form, rb) * (double)acc[b];
+      real ps, dps;
+      psi_pair(ph.psi_form, rhof[(size_t)b * N + i], ps, dps);
+      df[(size_t)b * N + i] += dps * (-ph.gab * acc[b]);
+      gab[0] -= (double)ps * (double)acc[b];
     }
   }
   block_sum_adj<1>(gab, sh);
@@ -546,9 +575,10 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
     for (int a = 0; a < 2; ++a) {
       real D = df[(size_t)a * N + i];
       if constexpr (FUSED) {
-        const real ra = rhof[(size_t)a * N + i];
-        D += dpsi_of(ph.psi_form, ra) * (-ph.gab * acc[a]);
-        gab[0] -= (double)psi_of(ph.psi_form, ra) * (double)acc[a];
+        real ps, dps;
+        psi_pair(ph.psi_form, rhof[(size_t)a * N + i], ps, dps);
+        D += dps * (-ph.gab * acc[a]);
+        gab[0] -= (double)ps * (double)acc[a];
       }
       const real E[3] = {ph.inv_tau[a] * e[0], ph.inv_tau[a] * e[1], ph.inv_tau[a] * e[2]};
       const real keep = real(1) - ph.inv_tau[a];
