@@ -12,8 +12,8 @@
 //      the vector e = dL/du' / R, from which dL/dj^a = e / tau^a, and
 //      accumulate the gradient of the wall parameters;
 //   2. per node: add the transposed force stencil, i.e. the gather
-//      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) to D (FP32: as
-//      a pass of its own), with the same gather giving the g_ab gradient
+//      -g_ab sum_k W_k q^b(y - c_k) . c_k, through psi'(rho) to D, with the
+//      same gather giving the g_ab gradient
 //      (-psi^b(y) times it, summed), then stream transposed with
 //      bounce-back, as a push of
 //      dL/dn_k = D + (e / tau) . c_k + (1 - 1/tau) lambda'_k to x - c_k (or
@@ -466,9 +466,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           accumulate ? partials[blockIdx.x * RED_STRIDE + c] + gp[c] : gp[c];
 }
 
-// D^b(y) += psi'(rho^b(y)) * (-g_ab sum_k W_k q^a(y - c_k) . c_k), a != b:
-// the transposed force stencil as a pass of its own (the FP32 path; the FP64
-// path does it inside the push-stream pass)
+// The gather of the transposed force stencil at fluid node y:
+// acc[b] = sum_k W_k q^a(y - c_k) . c_k, a != b, which adds
+// psi'(rho^b(y)) * (-g_ab acc[b]) to D^b(y)
 template <typename real>
 __device__ __forceinline__ void stencil_acc(const real* __restrict__ qf, int N,
                                             const int (&xs)[3], const int (&ys)[3],
@@ -498,41 +498,8 @@ __device__ __forceinline__ void stencil_acc(const real* __restrict__ qf, int N,
 // partials row.
 constexpr int GAB_COL = 5;
 
-template <typename real>
-__global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict__ links,
-                                                     const real* __restrict__ rhof, int nx, int ny,
-                                                     int nz, Phys<real> ph,
-                                                     const real* __restrict__ qf,
-                                                     real* __restrict__ df,
-                                                     double* __restrict__ partials,
-                                                     int accumulate) {
-  __shared__ double sh[16];
-  const int N = nx * ny * nz;
-  double gab[1] = {0};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-    if (links[i] & SELF_SOLID) continue;
-    int xs[3], ys[3], zs[3];
-    axis3(i % nx, nx, xs);
-    axis3((i / nx) % ny, ny, ys);
-    axis3(i / (nx * ny), nz, zs);
-    real acc[2];
-    stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      real ps, dps;
-      psi_pair(ph.psi_form, rhof[(size_t)b * N + i], ps, dps);
-      df[(size_t)b * N + i] += dps * (-ph.gab * acc[b]);
-      gab[0] -= (double)ps * (double)acc[b];
-    }
-  }
-  block_sum_adj<1>(gab, sh);
-  if (threadIdx.x == 0)
-    partials[blockIdx.x * RED_STRIDE + GAB_COL] =
-        accumulate ? partials[blockIdx.x * RED_STRIDE + GAB_COL] + gab[0] : gab[0];
-}
-
-// Transposed streaming (FUSED: with the transposed force stencil in the same
-// pass).  First, when FUSED, the non-local part of dL/drho at fluid node y,
+// Transposed streaming with the transposed force stencil in the same pass.
+// First the non-local part of dL/drho at fluid node y,
 // from q of the other species at the 18 upstream nodes:
 //   D^a(y) = D_local^a(y) + psi'(rho^a(y)) * (-g_ab sum_k W_k q^b(y - c_k) . c_k)
 // (only the components along which c_k moves are loaded: 60 loads).  Then
@@ -541,7 +508,7 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const uint32_t* __restrict_
 // forward step pulled n_k(y) from C_k(y - c_k)), and mu_{opp k}(y) goes to
 // lambda_k(y) itself when y + c_k is a wall (the forward step bounced C_k(y)
 // back into n_{opp k}(y)).  Every entry of lambda is written exactly once.
-template <typename real, bool FUSED>
+template <typename real>
 __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__ links, int nx,
                                                     int ny, int nz, Phys<real> ph,
                                                     const real* __restrict__ lam,
@@ -569,17 +536,14 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
       continue;
     }
     real acc[2] = {0, 0};
-    if constexpr (FUSED) stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
+    stencil_acc(qf, N, xs, ys, zs, nx, ny, ph, acc);
     const real e[3] = {ef[i], ef[(size_t)N + i], ef[2 * (size_t)N + i]};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      real D = df[(size_t)a * N + i];
-      if constexpr (FUSED) {
-        real ps, dps;
-        psi_pair(ph.psi_form, rhof[(size_t)a * N + i], ps, dps);
-        D += dps * (-ph.gab * acc[a]);
-        gab[0] -= (double)ps * (double)acc[a];
-      }
+      real ps, dps;
+      psi_pair(ph.psi_form, rhof[(size_t)a * N + i], ps, dps);
+      const real D = df[(size_t)a * N + i] + dps * (-ph.gab * acc[a]);
+      gab[0] -= (double)ps * (double)acc[a];
       const real E[3] = {ph.inv_tau[a] * e[0], ph.inv_tau[a] * e[1], ph.inv_tau[a] * e[2]};
       const real keep = real(1) - ph.inv_tau[a];
       real mu[Q];
@@ -605,17 +569,15 @@ __global__ __launch_bounds__(256) void k_adj_stream(const uint32_t* __restrict__
       }
     }
   }
-  if constexpr (FUSED) {
-    block_sum_adj<1>(gab, sh);
-    if (threadIdx.x == 0)
-      partials[blockIdx.x * RED_STRIDE + GAB_COL] =
-          accumulate ? partials[blockIdx.x * RED_STRIDE + GAB_COL] + gab[0] : gab[0];
-  }
+  block_sum_adj<1>(gab, sh);
+  if (threadIdx.x == 0)
+    partials[blockIdx.x * RED_STRIDE + GAB_COL] =
+        accumulate ? partials[blockIdx.x * RED_STRIDE + GAB_COL] + gab[0] : gab[0];
 }
 
 // Workgroups of the local pass (grid-stride over the nodes).  The FP64
-// kernel holds one wave per SIMD (its register set), so more workgroups
-// than two per CU only queue; the FP32 kernel fits several waves per SIMD.
+// kernel fits two waves per SIMD (its register set), so more workgroups
+// than two per CU only queue; the FP32 kernel fits three.
 static int adj_local_grid(size_t real_size) { return real_size == 8 ? 512 : 2048; }
 // The pass that gathers the transposed stencil (and with it the g_ab
 // gradient) runs one workgroup per 256 nodes up to ADJ_BLOCKS, each with its
@@ -651,17 +613,11 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
   else
     hipLaunchKernelGGL(k_adj_local<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s, jm,
                        lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
-  // FP64 adds the transposed stencil inside the push pass (one fewer sweep
-  // of D); in FP32 the gathers slow that pass more than the sweep costs.
-  // The pass that gathers the stencil has one row of g_ab partials per
-  // workgroup.
-  constexpr bool FUSED = sizeof(real) == 8;
+  // the transposed stencil inside the push pass (one sweep of D fewer than
+  // a pass of its own), with one row of g_ab partials per workgroup
   const int blocks = adj_gather_grid(N);
-  if (!FUSED)
-    hipLaunchKernelGGL(k_adj_stencil<real>, dim3(blocks), dim3(256), 0, s, links, rhof, nx, ny,
-                       nz, ph, qf, df, partials, accumulate);
-  hipLaunchKernelGGL((k_adj_stream<real, FUSED>), dim3(blocks), dim3(256), 0, s, links, nx, ny,
-                     nz, ph, lam_in, rhof, qf, df, ef, lam_out, partials, accumulate);
+  hipLaunchKernelGGL(k_adj_stream<real>, dim3(blocks), dim3(256), 0, s, links, nx, ny, nz, ph,
+                     lam_in, rhof, qf, df, ef, lam_out, partials, accumulate);
   return hipGetLastError();
 }
 
