@@ -604,9 +604,10 @@ static hipError_t adjoint_t(const real* C, const real* lam_in, real* lam_out,
     hipLaunchKernelGGL(k_stream_moments<real>, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256),
                        0, s, C, links, rhof, jf, nx, ny, nz);
   }
-  // FP64: the species-split local pass at two waves per SIMD (142.8 against
-  // 150.7 us on 128 x 128 x 64); FP32 fits three waves per SIMD with both
-  // species on one lane, and the split runs slower there (91.3 against 77.4)
+  // FP64: the species-split local pass at two waves per SIMD (144.9 against
+  // 150.7 us for one lane per node on 128 x 128 x 64); FP32 fits three waves
+  // per SIMD with both species on one lane, and the split runs slower there
+  // (80.1 against 50.4 us)
   if constexpr (sizeof(real) == 8)
     hipLaunchKernelGGL(k_adj_local_split<real>, dim3(adj_local_grid(sizeof(real))), dim3(256), 0, s,
                        jm, lam_in, links, rhof, nx, ny, nz, ph, qf, df, ef, partials, accumulate);
