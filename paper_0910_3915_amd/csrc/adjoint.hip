@@ -40,7 +40,7 @@ __device__ __forceinline__ void block_sum_adj(double (&v)[NV], double* sh) {
     }
 }
 
-// The pair forms below take velocity k + 1 as the opposite of k for odd k.
+// pair_moment below takes velocity k + 1 as the opposite of k for odd k.
 constexpr bool opposite_pairs_adjacent() {
   for (int k = 1; k < Q; k += 2)
     if (OPP[k] != k + 1 || CX[k + 1] != -CX[k] || CY[k + 1] != -CY[k] || CZ[k + 1] != -CZ[k])
